@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched FP16 matrix-core FFT on one MI355X.
+
+Workload (the paper's batched 1D case, Sec. 5.1: inputs uniform in [-1, 1],
+batch large enough to fill the GPU): N in {4096, 16384, 65536} with
+batch = 2^27 / N (512 MiB of FP16 complex input per size) plus 1 % unit-tone
+rows.  One step = one forward transform of each of the three batches.
+
+Metric: GFLOP/s with the 5 N log2 N convention, whole job; also HBM GB/s of the
+algorithmic traffic (8 B per point: one read and one write of FP16 complex) as
+a fraction of 8 TB/s.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SIZES = (4096, 16384, 65536)
+TOTAL_POINTS = 1 << 27
+
+
+def flops(n: int, batch: int) -> float:
+    return 5.0 * n * math.log2(n) * batch
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_launches(fn, reps: int, stream) -> float:
+    """Average duration (s) of fn() over reps, HIP events on `stream`."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps
+
+
+def accuracy_sample(plan, x_dev, y_dev, x_host, tones, rng, nsample=32):
+    """Relative L2 of sampled transforms (random rows + every tone row) vs the oracle."""
+    import oracle
+    batch = x_host.shape[0]
+    rows = np.unique(np.concatenate([rng.choice(batch, size=min(nsample, batch), replace=False),
+                                     tones.rows]))
+    y = y_dev[rows].cpu().numpy().astype(np.float64)
+    z = (y[..., 0] + 1j * y[..., 1]) * 2.0 ** plan.scale_log2
+    ref = oracle.fft(oracle.from_half(x_host[rows]), -1)
+    e = oracle.rel_l2(z, ref)
+    return float(e.max()), float(np.sqrt(np.mean(e ** 2))), oracle.eq5_error(z, ref), len(rows)
+
+
+def cpu_baseline(xs, target_s: float):
+    """The FP64 oracle (radix-2, C, OpenMP) on a bounded sample of the same
+    workload: the first rows of each size's batch, sized so the whole run takes
+    about target_s seconds of wall time."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    # calibration on a small slice
+    n0 = SIZES[0]
+    probe = oracle.from_half(xs[n0][0][:64])
+    t = time.perf_counter()
+    oracle.fft(probe, -1, threads)
+    dt = max(time.perf_counter() - t, 1e-4)
+    rate = flops(n0, 64) / dt  # flop/s
+    per_size = target_s / len(SIZES)
+    total_flop = 0.0
+    total_t = 0.0
+    parts = []
+    for n in SIZES:
+        rows = int(max(1, min(xs[n][0].shape[0], per_size * rate / flops(n, 1))))
+        z = oracle.from_half(xs[n][0][:rows])
+        t = time.perf_counter()
+        oracle.fft(z, -1, threads)
+        total_t += time.perf_counter() - t
+        total_flop += flops(n, rows)
+        parts.append(f"N={n} x {rows} rows")
+    return {"value": round(total_flop / total_t / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "FP64 radix-2 oracle on the first rows of each batch (" + ", ".join(parts)
+                      + f"), {total_t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); batched transforms "
+              "shard by transform with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_11471_amd import inputs, tcfft
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    plans, xs, xd, yd = {}, {}, {}, {}
+    for n in SIZES:
+        batch = TOTAL_POINTS // n
+        log(f"generating N={n} batch={batch}")
+        x, tones = inputs.batched_1d(n, batch, seed=0)
+        xs[n] = (x, tones)
+        xd[n] = torch.from_numpy(x).to(dev)
+        yd[n] = torch.empty_like(xd[n])
+        plans[n] = tcfft.Plan((n,), batch)
+        log(f"  plan {plans[n].describe()['passes']}")
+    torch.cuda.synchronize()
+
+    def step():
+        for n in SIZES:
+            plans[n](xd[n], yd[n], stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_flop = sum(flops(n, TOTAL_POINTS // n) for n in SIZES)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = total_flop * args.steps / elapsed / 1e9
+
+    # per-size timing (HIP events on the launch stream) and accuracy
+    per = {}
+    rng = np.random.default_rng(1)
+    for n in SIZES:
+        batch = TOTAL_POINTS // n
+        dt = time_launches(lambda: plans[n](xd[n], yd[n], stream=stream), 10, stream)
+        emax, erms, eq5, ns = accuracy_sample(plans[n], xd[n], yd[n], xs[n][0], xs[n][1], rng)
+        per[n] = {"us": round(dt * 1e6, 2), "gflops": round(flops(n, batch) / dt / 1e9, 1),
+                  "gbs_alg": round(8.0 * TOTAL_POINTS / dt / 1e9, 1),
+                  "launches": plans[n].num_launches,
+                  "rel_l2_max": emax, "rel_l2_rms": erms, "eq5": eq5, "rows_checked": ns}
+        log(f"N={n}: {per[n]}")
+
+    # dominant kernel: the single-launch size with the largest time
+    single = [n for n in SIZES if plans[n].num_launches == 1]
+    dom = max(single, key=lambda n: per[n]["us"])
+    dom_bytes = 8.0 * TOTAL_POINTS
+    dom_kernel = plans[dom].describe()["passes"][0]
+    achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"row_kernel<L={dom_kernel['L']}> N={dom} batch={TOTAL_POINTS // dom}"}
+
+    comparator = None
+    if not args.no_comparator:
+        n = SIZES[0]
+        batch = TOTAL_POINTS // n
+        p32 = tcfft.Plan((n,), batch, precision="fp32_radix2")
+        x32 = torch.from_numpy(xs[n][0].astype(np.float32)).to(dev)
+        y32 = torch.empty_like(x32)
+        p32(x32, y32, stream=stream)
+        dt = time_launches(lambda: p32(x32, y32, stream=stream), 3, stream)
+        comparator = {"N": n, "batch": batch, "us": round(dt * 1e6, 1),
+                      "gflops": round(flops(n, batch) / dt / 1e9, 1),
+                      "fp16_speedup": round((flops(n, batch) / (per[n]["us"] * 1e-6)) /
+                                            (flops(n, batch) / dt), 2)}
+        log(f"fp32 radix-2 comparator: {comparator}")
+        del x32, y32, p32
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(xs, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+
+    hbm_frac = 8.0 * TOTAL_POINTS * len(SIZES) * args.steps / elapsed / 1e9 / HBM_PEAK_GBS
+    line = {
+        "metric": "batched FP16 FFT GFLOP/s (5NlogN) & % HBM peak; mixed-size p99 latency",
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp16", "data": "synthetic",
+        "config": {"workload": "batched 1D complex FFT, N in {4096, 16384, 65536}, batch = 2^27/N "
+                               "(512 MiB FP16 each), uniform[-1,1] + 1% unit tones, forward",
+                   "points_per_size": TOTAL_POINTS, "precision": "fp16 storage, fp32 accumulate"},
+        "hbm_frac_alg": round(hbm_frac, 4),
+        "per_size": {str(k): v for k, v in per.items()},
+        "roofline": roofline,
+        "comparator_fp32_radix2": comparator,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,69 @@
+// Kernel parameter block and launch entry points shared by the device code
+// (kernels.hip) and the host runtime (tcfft.cpp).  No torch types anywhere.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcfft {
+
+// Parameters of one pass.  All element counts/strides are in complex points.
+struct KParams {
+  const uint32_t* in;      // FP16 complex words (split: hi plane)
+  uint32_t* out;
+  int64_t in_plane;        // split: offset of the lo plane from `in` (else 0)
+  int64_t out_plane;
+  int64_t ntrans;          // row kernel: number of transforms
+  const float2* tw;        // W_L^m, m in [0, L)   (direction folded in)
+  const void* fimg;        // radix-16 A-operand images (4 x 64 lanes x 8 halves)
+  float r0scale;           // scale of the radix-2/4/8 stage (power of two)
+  float sgn;               // -1 forward, +1 inverse
+  // column kernel geometry: element (j, c) of a tile at in_base + j*s_in + c
+  int64_t s_in, s_out;
+  int64_t blocks;          // column blocks per outer block
+  int64_t in_outer, out_outer;
+  int64_t q, qstride;      // output column base: (i0 / q) * qstride + (i0 % q)
+  // extra twiddle W_M^{ci * k} on the pass output, ci = (i0 + c) / xdiv
+  const float2* xtw_lo;    // W_M^e, e in [0, 2^xbits)
+  const float2* xtw_hi;    // W_M^{e * 2^xbits}, e in [0, M / 2^xbits)
+  int32_t xbits;
+  uint32_t xmask;          // M - 1
+  int64_t xdiv;
+};
+
+// Kernel variants.  `kind` selects the family, the rest are the template
+// parameters of that family (see kernels.hip).
+enum KernelKind { K_ROW = 0, K_COL = 1 };
+
+struct KernelKey {
+  int kind;    // KernelKind
+  int L;       // transform length handled in LDS
+  int R0;      // 1, 2, 4 or 8: radix of the vector-ALU stage
+  int C;       // column kernel: adjacent columns per workgroup (0 for row)
+  int NT;      // threads per workgroup
+  int split;   // 0 FP16, 1 split hi+lo
+  int xtw;     // column kernel: apply the extra inter-pass twiddle
+  int tstore;  // column kernel: transposed store (row of L contiguous outputs)
+};
+
+typedef void (*KernelFn)(KParams);
+
+// Returns the kernel for `key`, or nullptr when that variant is not compiled.
+KernelFn find_kernel(const KernelKey& key);
+// Dynamic LDS bytes the kernel needs.
+size_t kernel_lds_bytes(const KernelKey& key);
+// Points (complex elements) processed by one workgroup.
+int64_t kernel_points_per_wg(const KernelKey& key);
+
+// FP32 radix-2 Stockham comparator stage.
+void launch_radix2_stage(const float2* in, float2* out, int64_t n, int64_t ns, int64_t batch,
+                         const float2* tw, hipStream_t s);
+
+// FP64 table generators (run once per plan on the device).
+// tw[m] = exp(sgn * 2 pi i * ((m * mult) mod modulus) / modulus), rounded to FP32.
+void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mult, double sgn,
+                         hipStream_t s);
+// Radix-16 A-operand images, F scaled by `scale` (a power of two):
+// [0] Yr-hi, [1] Yi-hi, [2] Yr-lo, [3] Yi-lo; 64 lanes x 8 halves each.
+void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s);
+
+}  // namespace tcfft

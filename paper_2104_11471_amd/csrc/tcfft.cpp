@@ -1,0 +1,597 @@
+// Host runtime of libtcfft: planner, device tables, pass launcher and the C ABI
+// declared in include/tcfft.h.
+//
+// Plan mechanism (paper Sec. 3.1, Fig. 1): a plan fixes, once, the sequence of
+// merging kernels for a (rank, size, batch, precision, direction); the
+// execution function then launches that sequence.  Here a "pass" is one kernel
+// launch that does every merging process whose data fits in one workgroup's
+// LDS; passes exchange data through HBM (Sec. 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tcfft.h"
+#include "kernels.h"
+
+using namespace tcfft;
+
+namespace {
+
+constexpr int64_t kMaxPointsPerPlan = (int64_t)1 << 31;
+constexpr int kMaxRowL = 16384;  // largest single-pass contiguous length
+constexpr int kMaxColL = 2048;   // largest strided length handled in one pass
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int64_t n) {
+  int l = 0;
+  while (((int64_t)1 << l) < n) ++l;
+  return l;
+}
+
+// Radix split of a pass length L = R0 * 16^S (R0 in {1, 2, 4, 8}).
+int r0_of(int L) { return 1 << (ilog2(L) % 4); }
+int s16_of(int L) { return ilog2(L) / 4; }
+// Output scale exponent of one pass (unitary-like: 2^-2 per radix-16 stage,
+// 2^-1 for radix 2 or 4, 2^-2 for radix 8), so that FP16 never overflows.
+int pass_scale(int L) {
+  int r0 = r0_of(L);
+  return 2 * s16_of(L) + (r0 == 1 ? 0 : (r0 == 8 ? 2 : 1));
+}
+
+struct PassSpec {
+  KernelKey key;
+  int64_t grid = 0;
+  size_t lds = 0;
+  // geometry
+  int64_t ntrans = 0;  // row kernel
+  int64_t s_in = 0, s_out = 0, blocks = 0, in_outer = 0, out_outer = 0, q = 1, qstride = 0;
+  // extra twiddle
+  int64_t xmod = 0, xdiv = 1;
+  // buffers: 0 = user in, 1 = user out, 2 = workspace
+  int src = 0, dst = 1;
+  int scale = 0;  // this pass's scale exponent
+};
+
+struct Desc {
+  int rank = 1;
+  int64_t nx = 0, ny = 1;
+  int64_t batch = 0;
+  int dir = -1;
+  int prec = 0;
+  unsigned flags = 0;
+};
+
+struct PlanSpec {
+  Desc d;
+  int64_t npts = 0;  // points per transform
+  std::vector<PassSpec> passes;
+  int scale = 0;
+  size_t ws_bytes = 0;
+  size_t buf_bytes = 0;
+};
+
+tcfft_status col_choice(int L, int64_t inner, bool split, bool xtw, bool tstore, KernelKey* out) {
+  for (int C : {64, 32, 16, 8}) {
+    if (C > inner) continue;
+    for (int NT : {256, 128, 64}) {
+      KernelKey k{K_COL, L, r0_of(L), C, NT, split ? 1 : 0, xtw ? 1 : 0, tstore ? 1 : 0};
+      if (find_kernel(k) && kernel_lds_bytes(k) <= kMaxLds) {
+        *out = k;
+        return TCFFT_OK;
+      }
+    }
+  }
+  return TCFFT_ERR_UNSUPPORTED;
+}
+
+tcfft_status row_choice(int L, bool split, KernelKey* out) {
+  KernelKey k{K_ROW, L, r0_of(L), 0, 256, split ? 1 : 0, 0, 0};
+  if (!find_kernel(k) || kernel_lds_bytes(k) > kMaxLds) return TCFFT_ERR_UNSUPPORTED;
+  *out = k;
+  return TCFFT_OK;
+}
+
+// Row pass over `lines` contiguous lines of L points.
+tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst) {
+  PassSpec p;
+  tcfft_status st = row_choice(L, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key);
+  if (st) return st;
+  const int64_t tpb = kernel_points_per_wg(p.key) / L;
+  p.ntrans = lines;
+  p.grid = (lines + tpb - 1) / tpb;
+  p.lds = kernel_lds_bytes(p.key);
+  p.src = src;
+  p.dst = dst;
+  p.scale = pass_scale(L);
+  ps.passes.push_back(p);
+  return TCFFT_OK;
+}
+
+// Column pass: `outer` blocks of [L][inner]; input element (j, i) of block o at
+// o*in_outer + j*inner + i.  Output per mode (see KParams).
+tcfft_status add_col_pass(PlanSpec& ps, int L, int64_t inner, int64_t outer, int64_t in_outer,
+                          int64_t out_outer, int64_t s_out, int64_t q, int64_t qstride,
+                          bool tstore, int64_t xmod, int64_t xdiv, int src, int dst) {
+  PassSpec p;
+  const bool xtw = xmod > 0;
+  tcfft_status st = col_choice(L, inner, ps.d.prec == TCFFT_PREC_SPLIT_FP16, xtw, tstore, &p.key);
+  if (st) return st;
+  p.s_in = inner;
+  p.s_out = s_out;
+  p.blocks = inner / p.key.C;
+  p.in_outer = in_outer;
+  p.out_outer = out_outer;
+  p.q = q;
+  p.qstride = qstride;
+  p.xmod = xmod;
+  p.xdiv = xdiv;
+  p.grid = outer * p.blocks;
+  p.lds = kernel_lds_bytes(p.key);
+  p.src = src;
+  p.dst = dst;
+  p.scale = pass_scale(L);
+  ps.passes.push_back(p);
+  return TCFFT_OK;
+}
+
+// Splits a long 1D length into pass lengths (each <= kMaxColL), most balanced first.
+std::vector<int> long_split(int64_t n) {
+  const int lg = ilog2(n);
+  const int lmax = ilog2(kMaxColL);
+  const int np = (lg + lmax - 1) / lmax;
+  std::vector<int> f;
+  int rem = lg;
+  for (int i = 0; i < np; ++i) {
+    int e = rem / (np - i);
+    f.push_back(1 << e);
+    rem -= e;
+  }
+  // larger factors last: the last pass writes with the widest contiguous runs
+  std::sort(f.begin(), f.end());
+  return f;
+}
+
+tcfft_status validate(const Desc& d) {
+  if (d.rank != 1 && d.rank != 2) return TCFFT_ERR_INVALID_ARG;
+  if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
+  if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
+  if (d.prec < 0 || d.prec > 2) return TCFFT_ERR_INVALID_ARG;
+  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH)) return TCFFT_ERR_INVALID_ARG;
+  if (d.nx <= 0 || d.ny <= 0) return TCFFT_ERR_INVALID_ARG;
+  if (!is_pow2(d.nx) || !is_pow2(d.ny)) return TCFFT_ERR_UNSUPPORTED;
+  if (d.rank == 1) {
+    if (d.nx < 16 || d.nx > ((int64_t)1 << 27)) return TCFFT_ERR_UNSUPPORTED;
+  } else {
+    if (d.nx < 16 || d.nx > kMaxColL || d.ny < 16 || d.ny > kMaxRowL) return TCFFT_ERR_UNSUPPORTED;
+    if (d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  }
+  const int64_t npts = d.nx * d.ny;
+  if (d.batch > kMaxPointsPerPlan / npts) return TCFFT_ERR_UNSUPPORTED;
+  return TCFFT_OK;
+}
+
+tcfft_status build_spec(const Desc& d, PlanSpec* out) {
+  tcfft_status st = validate(d);
+  if (st) return st;
+  PlanSpec ps;
+  ps.d = d;
+  ps.npts = d.nx * d.ny;
+  const int64_t B = d.batch;
+  const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
+  ps.buf_bytes = (size_t)(ps.npts * B) * elt;
+  if (d.prec == TCFFT_PREC_FP32_RADIX2) {
+    ps.ws_bytes = ps.buf_bytes;
+    ps.scale = 0;
+    *out = ps;
+    return TCFFT_OK;
+  }
+  if (d.rank == 1) {
+    const int64_t N = d.nx;
+    if (N <= kMaxRowL) {
+      st = add_row_pass(ps, (int)N, B, 0, 1);
+    } else {
+      std::vector<int> f = long_split(N);
+      if (f.size() == 2) {
+        const int64_t N1 = f[0], N2 = f[1];
+        // pass 1: N1-point DFTs over n1 (stride N2), twiddle W_N^{n2 k1},
+        // transposed store Z[n2][k1]
+        st = add_col_pass(ps, (int)N1, N2, B, N, N, 0, 1, 0, true, N, 1, 0, 2);
+        // pass 2: N2-point DFTs over n2 (stride N1) -> X[k2 N1 + k1]
+        if (!st) st = add_col_pass(ps, (int)N2, N1, B, N, N, N1, N1, 0, false, 0, 1, 2, 1);
+      } else if (f.size() == 3) {
+        const int64_t N1 = f[0], N2 = f[1], N3 = f[2];
+        // pass 1: over n1 (stride N2 N3), twiddle W_N^{(n2 N3 + n3) k1},
+        // transposed store Z1[n2][n3][k1]
+        st = add_col_pass(ps, (int)N1, N2 * N3, B, N, N, 0, 1, 0, true, N, 1, 0, 2);
+        // pass 2: over n2 (stride N3 N1), twiddle W_{N2 N3}^{n3 k2}, store
+        // Z2[n3][k2][k1] (into the output buffer)
+        if (!st)
+          st = add_col_pass(ps, (int)N2, N3 * N1, B, N, N, N1, N1, N2 * N1, false, N2 * N3, N1, 2, 1);
+        // pass 3: over n3 (stride N2 N1) -> X[k3 N1 N2 + k2 N1 + k1], in place
+        if (!st)
+          st = add_col_pass(ps, (int)N3, N2 * N1, B, N, N, N2 * N1, N2 * N1, 0, false, 0, 1, 1, 1);
+      } else {
+        st = TCFFT_ERR_UNSUPPORTED;
+      }
+      ps.ws_bytes = ps.buf_bytes;
+    }
+  } else {
+    const int64_t nx = d.nx, ny = d.ny;
+    // rows: B*nx contiguous ny-point transforms; then columns: B blocks of
+    // [nx][ny], strided nx-point transforms, in place in the output
+    st = add_row_pass(ps, (int)ny, B * nx, 0, 1);
+    if (!st) st = add_col_pass(ps, (int)nx, ny, B, nx * ny, nx * ny, ny, ny, 0, false, 0, 1, 1, 1);
+  }
+  if (st) return st;
+  if (d.flags & TCFFT_FLAG_NO_SCALE)
+    for (auto& p : ps.passes) p.scale = 0;
+  ps.scale = 0;
+  for (auto& p : ps.passes) ps.scale += p.scale;
+  *out = ps;
+  return TCFFT_OK;
+}
+
+std::string describe(const PlanSpec& ps) {
+  static const char* precs[] = {"fp16", "split_fp16", "fp32_radix2"};
+  char b[512];
+  std::string s;
+  std::snprintf(b, sizeof b,
+                "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
+                "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,\"passes\":[",
+                ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
+                ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
+                precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes);
+  s += b;
+  if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
+    std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
+    s += b;
+  }
+  for (size_t i = 0; i < ps.passes.size(); ++i) {
+    const PassSpec& p = ps.passes[i];
+    std::string rad = "[";
+    int r0 = p.key.R0, s16 = s16_of(p.key.L);
+    bool first = true;
+    if (r0 > 1) {
+      rad += std::to_string(r0);
+      first = false;
+    }
+    for (int k = 0; k < s16; ++k) {
+      rad += first ? "16" : ",16";
+      first = false;
+    }
+    rad += "]";
+    std::snprintf(b, sizeof b,
+                  "%s{\"kernel\":\"%s\",\"L\":%d,\"radices\":%s,\"C\":%d,\"NT\":%d,\"grid\":%lld,"
+                  "\"lds\":%zu,\"xtw\":%d,\"tstore\":%d,\"scale\":%d,\"src\":%d,\"dst\":%d,"
+                  "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld}",
+                  i ? "," : "", p.key.kind == K_ROW ? "row" : "col", p.key.L, rad.c_str(), p.key.C,
+                  p.key.NT, (long long)p.grid, p.lds, p.key.xtw, p.key.tstore, p.scale, p.src,
+                  p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod);
+    s += b;
+  }
+  s += "]}";
+  return s;
+}
+
+int copy_out(const std::string& s, char* buf, size_t len) {
+  if (buf && len) {
+    size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return (int)s.size();
+}
+
+// ---------------------------------------------------------------------------
+// Device side of a plan.
+struct DevPass {
+  PassSpec spec;
+  KernelFn fn = nullptr;
+  float2* tw = nullptr;      // W_L^m
+  float2* xtw_lo = nullptr;  // two-level W_M tables
+  float2* xtw_hi = nullptr;
+  int xbits = 0;
+};
+
+}  // namespace
+
+struct tcfft_plan_s {
+  PlanSpec spec;
+  int device = 0;
+  std::vector<DevPass> dp;
+  void* fimg = nullptr;     // radix-16 A operands (pass-independent: one scale variant)
+  void* ws = nullptr;
+  float2* r2tw = nullptr;   // FP32 radix-2 comparator: W_N^m
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+tcfft_status dev_alloc(tcfft_plan_s* p, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return TCFFT_OK;
+  if (std::getenv("TCFFT_TEST_FAIL_ALLOC")) return TCFFT_ERR_ALLOC;
+  if (hipMalloc(out, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return TCFFT_ERR_ALLOC;
+  }
+  p->allocs.push_back(*out);
+  return TCFFT_OK;
+}
+
+void free_plan(tcfft_plan_s* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  for (void* a : p->allocs) (void)hipFree(a);
+  delete p;
+}
+
+tcfft_status check_device(int* dev) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_NO_DEVICE;
+  }
+  if (hipGetDevice(dev) != hipSuccess) return TCFFT_ERR_NO_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return TCFFT_ERR_NO_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TCFFT_ERR_NO_DEVICE;
+  return TCFFT_OK;
+}
+
+std::mutex g_attr_mu;
+
+tcfft_status prepare_kernel(KernelFn fn, size_t lds) {
+  if (lds <= 65536) return TCFFT_OK;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_LAUNCH;
+  }
+  return TCFFT_OK;
+}
+
+tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
+  PlanSpec ps;
+  tcfft_status st = build_spec(d, &ps);
+  if (st) return st;
+  int dev = 0;
+  st = check_device(&dev);
+  if (st) return st;
+  tcfft_plan_s* p = new tcfft_plan_s();
+  p->spec = ps;
+  p->device = dev;
+  const double sgn = (double)d.dir;
+  hipStream_t s = nullptr;
+  do {
+    if (d.prec == TCFFT_PREC_FP32_RADIX2) {
+      void* t = nullptr;
+      if ((st = dev_alloc(p, (size_t)(ps.npts / 2) * sizeof(float2), &t))) break;
+      p->r2tw = (float2*)t;
+      launch_gen_twiddles(p->r2tw, ps.npts / 2, ps.npts, 1, sgn, s);
+      if ((st = dev_alloc(p, ps.ws_bytes, &p->ws))) break;
+      break;
+    }
+    if ((st = dev_alloc(p, 4 * 64 * 16, &p->fimg))) break;
+    const bool noscale = (d.flags & TCFFT_FLAG_NO_SCALE) != 0;
+    launch_gen_fimg(p->fimg, sgn, noscale ? 1.0 : 0.25, s);
+    for (const PassSpec& sp : ps.passes) {
+      DevPass dpp;
+      dpp.spec = sp;
+      dpp.fn = find_kernel(sp.key);
+      if (!dpp.fn) {
+        st = TCFFT_ERR_INTERNAL;
+        break;
+      }
+      if ((st = prepare_kernel(dpp.fn, sp.lds))) break;
+      void* t = nullptr;
+      if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
+      dpp.tw = (float2*)t;
+      launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
+      if (sp.xmod > 0) {
+        const int lg = ilog2(sp.xmod);
+        dpp.xbits = (lg + 1) / 2;
+        const int64_t nlo = (int64_t)1 << dpp.xbits, nhi = sp.xmod >> dpp.xbits;
+        if ((st = dev_alloc(p, (size_t)nlo * sizeof(float2), &t))) break;
+        dpp.xtw_lo = (float2*)t;
+        if ((st = dev_alloc(p, (size_t)nhi * sizeof(float2), &t))) break;
+        dpp.xtw_hi = (float2*)t;
+        launch_gen_twiddles(dpp.xtw_lo, nlo, sp.xmod, 1, sgn, s);
+        launch_gen_twiddles(dpp.xtw_hi, nhi, sp.xmod, nlo, sgn, s);
+      }
+      p->dp.push_back(dpp);
+    }
+    if (st) break;
+    if ((st = dev_alloc(p, ps.ws_bytes, &p->ws))) break;
+  } while (false);
+  if (!st && hipGetLastError() != hipSuccess) st = TCFFT_ERR_LAUNCH;
+  if (!st && hipDeviceSynchronize() != hipSuccess) st = TCFFT_ERR_LAUNCH;
+  if (st) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return TCFFT_OK;
+}
+
+tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  const PlanSpec& ps = p->spec;
+  if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
+    const int T = ilog2(ps.npts);
+    const float2* src = (const float2*)in;
+    float2* ws = (float2*)p->ws;
+    float2* o = (float2*)out;
+    for (int st = 0; st < T; ++st) {
+      // the last stage lands in `out`; earlier ones alternate so that no stage
+      // reads and writes the same buffer
+      float2* dst = ((T - 1 - st) % 2 == 0) ? o : ws;
+      if (st == 0 && dst == src) dst = ws;
+      if (st > 0 && dst == src) dst = (dst == o) ? ws : o;
+      launch_radix2_stage(src, dst, ps.npts, (int64_t)1 << st, ps.d.batch, p->r2tw, s);
+      src = dst;
+    }
+    if (src != o)
+      if (hipMemcpyAsync(o, src, ps.buf_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return TCFFT_ERR_LAUNCH;
+    return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
+  }
+  const int64_t plane = ps.npts * ps.d.batch;
+  const bool split = ps.d.prec == TCFFT_PREC_SPLIT_FP16;
+  for (const DevPass& dpp : p->dp) {
+    const PassSpec& sp = dpp.spec;
+    auto buf = [&](int which) -> uint32_t* {
+      return which == 0 ? (uint32_t*)in : which == 1 ? (uint32_t*)out : (uint32_t*)p->ws;
+    };
+    KParams kp{};
+    kp.in = buf(sp.src);
+    kp.out = buf(sp.dst);
+    kp.in_plane = split ? plane : 0;
+    kp.out_plane = split ? plane : 0;
+    kp.ntrans = sp.ntrans;
+    kp.tw = dpp.tw;
+    kp.fimg = p->fimg;
+    kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
+    if (ps.d.flags & TCFFT_FLAG_NO_SCALE) kp.r0scale = 1.0f;
+    kp.sgn = (float)ps.d.dir;
+    kp.s_in = sp.s_in;
+    kp.s_out = sp.s_out;
+    kp.blocks = sp.blocks;
+    kp.in_outer = sp.in_outer;
+    kp.out_outer = sp.out_outer;
+    kp.q = sp.q;
+    kp.qstride = sp.qstride;
+    kp.xtw_lo = dpp.xtw_lo;
+    kp.xtw_hi = dpp.xtw_hi;
+    kp.xbits = dpp.xbits;
+    kp.xmask = (uint32_t)(sp.xmod > 0 ? sp.xmod - 1 : 0);
+    kp.xdiv = sp.xdiv;
+    void* args[] = {&kp};
+    if (hipLaunchKernel((const void*)dpp.fn, dim3((unsigned)sp.grid), dim3(sp.key.NT), args,
+                        sp.lds, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_LAUNCH;
+    }
+  }
+  return TCFFT_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+tcfft_status tcfft_plan_create(tcfft_plan* out, int rank, const int64_t* dims, int64_t batch,
+                               int dir, int precision, unsigned flags) {
+  if (!out || !dims) return TCFFT_ERR_INVALID_ARG;
+  *out = nullptr;
+  Desc d;
+  d.rank = rank;
+  if (rank != 1 && rank != 2) return TCFFT_ERR_INVALID_ARG;
+  d.nx = dims[0];
+  d.ny = rank == 2 ? dims[1] : 1;
+  d.batch = batch;
+  d.dir = dir;
+  d.prec = precision;
+  d.flags = flags;
+  try {
+    return create_impl(d, out);
+  } catch (...) {
+    return TCFFT_ERR_INTERNAL;
+  }
+}
+
+tcfft_status tcfft_plan_1d(tcfft_plan* out, int64_t nx, int64_t batch) {
+  int64_t dims[1] = {nx};
+  return tcfft_plan_create(out, 1, dims, batch, TCFFT_FORWARD, TCFFT_PREC_FP16, 0);
+}
+
+tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batch) {
+  int64_t dims[2] = {nx, ny};
+  return tcfft_plan_create(out, 2, dims, batch, TCFFT_FORWARD, TCFFT_PREC_FP16, 0);
+}
+
+tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream) {
+  if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
+  return exec_impl(plan, in, out, (hipStream_t)stream);
+}
+
+tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
+                             int njobs, void* stream) {
+  if (njobs < 0 || (njobs > 0 && (!plans || !in || !out))) return TCFFT_ERR_INVALID_ARG;
+  for (int j = 0; j < njobs; ++j)
+    if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]))
+      return TCFFT_ERR_INVALID_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    tcfft_status st = exec_impl(plans[j], in[j], out[j], (hipStream_t)stream);
+    if (st) return st;
+  }
+  return TCFFT_OK;
+}
+
+tcfft_status tcfft_plan_destroy(tcfft_plan plan) {
+  free_plan(plan);
+  return TCFFT_OK;
+}
+
+int tcfft_plan_scale_log2(tcfft_plan plan) { return plan ? plan->spec.scale : -1; }
+
+size_t tcfft_plan_buffer_bytes(tcfft_plan plan) { return plan ? plan->spec.buf_bytes : 0; }
+
+size_t tcfft_plan_workspace_bytes(tcfft_plan plan) { return plan ? plan->spec.ws_bytes : 0; }
+
+int tcfft_plan_num_launches(tcfft_plan plan) {
+  if (!plan) return -1;
+  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return ilog2(plan->spec.npts);
+  return (int)plan->spec.passes.size();
+}
+
+int tcfft_plan_describe(tcfft_plan plan, char* buf, size_t len) {
+  if (!plan) return -1;
+  return copy_out(describe(plan->spec), buf, len);
+}
+
+int tcfft_plan_dry_run(int rank, const int64_t* dims, int64_t batch, int dir, int precision,
+                       unsigned flags, char* buf, size_t len) {
+  if (!dims || (rank != 1 && rank != 2)) return -(int)TCFFT_ERR_INVALID_ARG;
+  Desc d;
+  d.rank = rank;
+  d.nx = dims[0];
+  d.ny = rank == 2 ? dims[1] : 1;
+  d.batch = batch;
+  d.dir = dir;
+  d.prec = precision;
+  d.flags = flags;
+  PlanSpec ps;
+  tcfft_status st = build_spec(d, &ps);
+  if (st) return -(int)st;
+  return copy_out(describe(ps), buf, len);
+}
+
+const char* tcfft_status_string(tcfft_status s) {
+  switch (s) {
+    case TCFFT_OK: return "ok";
+    case TCFFT_ERR_INVALID_ARG: return "invalid argument";
+    case TCFFT_ERR_UNSUPPORTED: return "unsupported size or configuration";
+    case TCFFT_ERR_NO_DEVICE: return "no gfx950 device";
+    case TCFFT_ERR_ALLOC: return "device allocation failed";
+    case TCFFT_ERR_LAUNCH: return "kernel launch failed";
+    case TCFFT_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* tcfft_version(void) { return "tcfft-mi355x 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+"""Thin ctypes binding of libtcfft.so (argument marshalling only).
+
+Every step of a transform runs in the library's HIP kernels; torch provides
+device memory and the current stream, nothing else.  Importing this module
+loads the library and raises ``RuntimeError`` when it is missing: there is no
+fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtcfft.so")
+
+FORWARD = -1
+INVERSE = 1
+PREC_FP16 = 0
+PREC_SPLIT_FP16 = 1
+PREC_FP32_RADIX2 = 2
+FLAG_NO_SCALE = 1
+FLAG_NO_GRAPH = 2
+_PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_FP16,
+         "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "alloc",
+          5: "launch", 6: "internal"}
+
+# every symbol include/tcfft.h declares
+EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", "tcfft_exec_many",
+           "tcfft_plan_destroy", "tcfft_plan_scale_log2", "tcfft_plan_buffer_bytes",
+           "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
+           "tcfft_plan_dry_run", "tcfft_status_string", "tcfft_version"]
+
+
+class TcfftError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m "
+                           "paper_2104_11471_amd.build` (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64 = ctypes.c_int64
+    vp = ctypes.c_void_p
+    P = ctypes.POINTER
+    lib.tcfft_plan_create.argtypes = [P(vp), ctypes.c_int, P(i64), i64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint]
+    lib.tcfft_plan_1d.argtypes = [P(vp), i64, i64]
+    lib.tcfft_plan_2d.argtypes = [P(vp), i64, i64, i64]
+    lib.tcfft_exec.argtypes = [vp, vp, vp, vp]
+    lib.tcfft_exec_many.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
+    lib.tcfft_plan_destroy.argtypes = [vp]
+    lib.tcfft_plan_scale_log2.argtypes = [vp]
+    lib.tcfft_plan_buffer_bytes.argtypes = [vp]
+    lib.tcfft_plan_buffer_bytes.restype = ctypes.c_size_t
+    lib.tcfft_plan_workspace_bytes.argtypes = [vp]
+    lib.tcfft_plan_workspace_bytes.restype = ctypes.c_size_t
+    lib.tcfft_plan_num_launches.argtypes = [vp]
+    lib.tcfft_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.tcfft_plan_dry_run.argtypes = [ctypes.c_int, P(i64), i64, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_uint, ctypes.c_char_p, ctypes.c_size_t]
+    lib.tcfft_status_string.argtypes = [ctypes.c_int]
+    lib.tcfft_status_string.restype = ctypes.c_char_p
+    lib.tcfft_version.argtypes = []
+    lib.tcfft_version.restype = ctypes.c_char_p
+    for name in ("tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec",
+                 "tcfft_exec_many", "tcfft_plan_destroy", "tcfft_plan_scale_log2",
+                 "tcfft_plan_num_launches", "tcfft_plan_describe", "tcfft_plan_dry_run"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _prec(p) -> int:
+    return _PREC[p] if isinstance(p, str) else int(p)
+
+
+def dry_run(dims, batch: int, direction: int = FORWARD, precision="fp16", flags: int = 0) -> dict:
+    """Planner only (no device): the JSON plan the arguments would produce."""
+    dims = tuple(int(d) for d in dims)
+    arr = (ctypes.c_int64 * len(dims))(*dims)
+    buf = ctypes.create_string_buffer(8192)
+    n = lib.tcfft_plan_dry_run(len(dims), arr, int(batch), int(direction), _prec(precision),
+                               int(flags), buf, len(buf))
+    if n < 0:
+        raise TcfftError(-n, "tcfft_plan_dry_run")
+    return json.loads(buf.value.decode())
+
+
+class Plan:
+    """A tcFFT plan: ``Plan((n,), batch)`` or ``Plan((nx, ny), batch)``.
+
+    Tensors (torch, on the plan's device):
+      * fp16: ``float16`` of shape ``(batch, *dims, 2)`` (interleaved re, im);
+      * split: ``float16`` of shape ``(2, batch, *dims, 2)`` -- hi plane then lo
+        plane, value = hi + 2^-11 lo;
+      * fp32_radix2: ``float32`` of shape ``(batch, n, 2)``.
+    The output holds DFT(x) * 2^-scale_log2 in the same layout."""
+
+    def __init__(self, dims, batch: int, direction: int = FORWARD, precision="fp16",
+                 flags: int = 0):
+        self.dims = tuple(int(d) for d in dims)
+        self.batch = int(batch)
+        self.direction = int(direction)
+        self.precision = _prec(precision)
+        self.flags = int(flags)
+        arr = (ctypes.c_int64 * len(self.dims))(*self.dims)
+        h = ctypes.c_void_p()
+        st = lib.tcfft_plan_create(ctypes.byref(h), len(self.dims), arr, self.batch,
+                                   self.direction, self.precision, self.flags)
+        if st != 0:
+            raise TcfftError(st, "tcfft_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def scale_log2(self) -> int:
+        return int(lib.tcfft_plan_scale_log2(self._h))
+
+    @property
+    def buffer_bytes(self) -> int:
+        return int(lib.tcfft_plan_buffer_bytes(self._h))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib.tcfft_plan_workspace_bytes(self._h))
+
+    @property
+    def num_launches(self) -> int:
+        return int(lib.tcfft_plan_num_launches(self._h))
+
+    def describe(self) -> dict:
+        buf = ctypes.create_string_buffer(8192)
+        lib.tcfft_plan_describe(self._h, buf, len(buf))
+        return json.loads(buf.value.decode())
+
+    def shape(self) -> tuple:
+        if self.precision == PREC_SPLIT_FP16:
+            return (2, self.batch, *self.dims, 2)
+        return (self.batch, *self.dims, 2)
+
+    def dtype(self):
+        import torch
+        return torch.float32 if self.precision == PREC_FP32_RADIX2 else torch.float16
+
+    def empty(self, device=None):
+        import torch
+        return torch.empty(self.shape(), dtype=self.dtype(), device=device or "cuda")
+
+    def _check(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != self.dtype() or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype()} tensor")
+        if t.numel() * t.element_size() != self.buffer_bytes:
+            raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, "
+                             f"the plan needs {self.buffer_bytes}")
+
+    def exec_raw(self, in_ptr: int, out_ptr: int, stream_ptr: int) -> None:
+        st = lib.tcfft_exec(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                            ctypes.c_void_p(stream_ptr))
+        if st != 0:
+            raise TcfftError(st, "tcfft_exec")
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        self._check(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(out, "output")
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        self.exec_raw(x.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.tcfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exec_many(plans, xs, outs, stream=None) -> None:
+    """Runs plans[j] on (xs[j], outs[j]) for all j in one call."""
+    import torch
+    n = len(plans)
+    VP = ctypes.c_void_p
+    hp = (VP * n)(*[p.handle for p in plans])
+    ip = (VP * n)(*[x.data_ptr() for x in xs])
+    op = (VP * n)(*[o.data_ptr() for o in outs])
+    for p, x, o in zip(plans, xs, outs):
+        p._check(x, "input")
+        p._check(o, "output")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib.tcfft_exec_many(hp, ip, op, n, VP(s.cuda_stream))
+    if st != 0:
+        raise TcfftError(st, "tcfft_exec_many")

@@ -1,0 +1,131 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: relative L2 per transform <= 5e-3 (FP16 storage), <= 2e-5 (split
+hi+lo FP16), <= 1e-5 (FP32 radix-2 comparator)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_11471_amd import inputs
+from tests.gpu_util import FP16_TOL, FP32_TOL, SPLIT_TOL, log, reference, rel_err, run_plan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2104_11471_amd import tcfft
+    return tcfft
+
+
+def _check(tc, dims, batch, prec="fp16", sign=-1, flags=0, seed=0, tol=None, inplace=False):
+    rank = len(dims)
+    log(f"case dims={dims} batch={batch} prec={prec} sign={sign} flags={flags} seed={seed}")
+    if prec == "split":
+        x = inputs.to_split(inputs.uniform_f64((batch, *dims), seed))
+        tol = tol or SPLIT_TOL
+    elif prec == "fp32_radix2":
+        x = inputs.uniform((batch, *dims), seed).astype(np.float32)
+        tol = tol or FP32_TOL
+    else:
+        x = inputs.uniform((batch, *dims), seed)
+        tol = tol or FP16_TOL
+    plan = tc.Plan(dims, batch, direction=sign, precision=prec, flags=flags)
+    y = run_plan(plan, x, inplace=inplace)
+    ref = reference(x, rank, sign)
+    e = rel_err(y, ref, rank)
+    log(f"  max rel L2 = {e.max():.3e}  mean = {e.mean():.3e}  S = {plan.scale_log2}")
+    assert np.all(np.isfinite(y))
+    assert e.max() <= tol, (dims, batch, prec, float(e.max()))
+    return e
+
+
+def test_radix16_block_is_the_dft_matrix(tc):
+    """N = 16: one matrix-core block.  Input delta at r must give row r of the
+    DFT matrix W_16^{r k} (probes the operand and accumulator layouts)."""
+    x = np.zeros((16, 16, 2), np.float16)
+    for r in range(16):
+        x[r, r, 0] = 1.0
+    plan = tc.Plan((16,), 16, flags=tc.FLAG_NO_SCALE)
+    y = run_plan(plan, x)
+    k = np.arange(16)
+    for r in range(16):
+        ref = np.exp(-2j * np.pi * ((r * k) % 16) / 16)
+        assert np.abs(y[r] - ref).max() < 2e-3, r
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])
+def test_single_pass_sizes(tc, n):
+    _check(tc, (n,), 37)       # ragged batch: not a multiple of lines per workgroup
+
+
+@pytest.mark.parametrize("n", [1 << 15, 1 << 16, 1 << 17, 1 << 20, 1 << 22, 1 << 23])
+def test_multi_pass_sizes(tc, n):
+    _check(tc, (n,), 3 if n <= (1 << 20) else 1)
+
+
+def test_config1_exact_shape(tc):
+    """N=256, batch 64, uniform[-1,1] from seed 0, unnormalised (S = 0)."""
+    e = _check(tc, (256,), 64, flags=tc.FLAG_NO_SCALE, seed=0)
+    assert e.shape == (64,)
+
+
+@pytest.mark.parametrize("n", [256, 4096, 1 << 16])
+def test_inverse_and_roundtrip(tc, n):
+    _check(tc, (n,), 5, sign=1)
+    x = inputs.uniform((4, n), 3)
+    f = tc.Plan((n,), 4, direction=-1)
+    b = tc.Plan((n,), 4, direction=1)
+    import torch
+    t = torch.from_numpy(x).cuda()
+    y = b(f(t))
+    torch.cuda.synchronize()
+    z = y.cpu().numpy().astype(np.float64)
+    z = (z[..., 0] + 1j * z[..., 1]) * 2.0 ** (f.scale_log2 + b.scale_log2)
+    e = oracle.rel_l2(z, n * oracle.from_half(x))
+    assert e.max() < 2 * FP16_TOL
+
+
+@pytest.mark.parametrize("dims", [(16, 16), (64, 512), (256, 256), (512, 128), (1024, 1024),
+                                  (2048, 16)])
+def test_2d(tc, dims):
+    _check(tc, dims, 3 if dims[0] * dims[1] <= 65536 else 1)
+
+
+@pytest.mark.parametrize("dims", [(256,), (4096,), (16384,), (1 << 16,), (1 << 20,), (128, 128),
+                                  (512, 512)])
+def test_split_precision(tc, dims):
+    _check(tc, dims, 3 if np.prod(dims) <= 65536 else 1, prec="split")
+
+
+@pytest.mark.parametrize("n", [16, 256, 4096, 1 << 16])
+def test_fp32_radix2_comparator(tc, n):
+    _check(tc, (n,), 5, prec="fp32_radix2")
+    _check(tc, (n,), 2, prec="fp32_radix2", inplace=True)
+
+
+@pytest.mark.parametrize("dims", [(4096,), (1 << 16,), (256, 256)])
+def test_in_place(tc, dims):
+    _check(tc, dims, 3, inplace=True)
+
+
+def test_deterministic(tc):
+    import torch
+    x = torch.from_numpy(inputs.uniform((64, 4096), 1)).cuda()
+    p = tc.Plan((4096,), 64)
+    a = p(x).cpu().numpy()
+    b = p(x).cpu().numpy()
+    assert np.array_equal(a.view(np.uint16), b.view(np.uint16))
+
+
+def test_tone_rows(tc):
+    """Unit tones x[n] = exp(+2 pi i f n/N): the peak lands at bin f with |Y_f| 2^S ~ N."""
+    n, batch = 4096, 200
+    x, tones = inputs.batched_1d(n, batch, seed=0)
+    p = tc.Plan((n,), batch)
+    y = run_plan(p, x)
+    for r, f in zip(tones.rows, tones.freqs):
+        assert int(np.argmax(np.abs(y[r]))) == int(f)
+        assert abs(abs(y[r, f]) - n) / n < 5e-3
+        off = np.delete(np.abs(y[r]) ** 2, f).sum() / (n * n)
+        assert off < 1e-4
