@@ -31,11 +31,14 @@
 namespace tcfft {
 
 // ---------------------------------------------------------------------------
-// LDS addressing.  Position p (in complex words) -> word address.  The swizzle
-// XORs address bits [4,6) with bits [8,10) so that groups of 4 consecutive
-// words stay 16-byte aligned for ds_read/write_b128 while chunks that sit 1 KB
-// apart move to different banks.
-__device__ __forceinline__ int lds_addr(int p) { return p ^ (((p >> 8) & 3) << 4); }
+// LDS addressing.  Position p (in complex words) -> word address.  Bits [2,6)
+// (the 16-byte group inside a 256-byte bank row) are XORed with a fold of the
+// bits above, so 16-byte groups stay aligned for ds_read/write_b128 while
+// accesses whose positions differ only above bit 6 (long strides, the
+// digit-reversed last stage, the transposed gather) spread over the banks.
+__device__ __forceinline__ int lds_addr(int p) {
+  return p ^ ((((p >> 6) ^ (p >> 10) ^ (p >> 14)) & 15) << 2);
+}
 
 __device__ __forceinline__ u4 lds_ld4(const uint32_t* lds, int p) {
   return *reinterpret_cast<const u4*>(lds + lds_addr(p));
@@ -56,10 +59,10 @@ template <int R0, int S>
 __device__ __forceinline__ int posrev_hi(int klow) {
   int k0 = klow % R0;
   int m = klow / R0;
-  int hi = k0 * pow16(S - 1);
+  int hi = k0 << (4 * (S - 1));
 #pragma unroll
   for (int s = 1; s < S; ++s) {
-    hi += (m & 15) * pow16(S - 1 - s);
+    hi += (m & 15) << (4 * (S - 1 - s));
     m >>= 4;
   }
   return hi;
@@ -121,7 +124,8 @@ struct RowGeom {
   static constexpr int L = L_, R0 = R0_, NT = NT_;
   static constexpr int S = (ilog2c(L) - ilog2c(R0)) / 4;
   static_assert(pow16(S) * R0 == L, "L must be R0 * 16^S");
-  static constexpr int TPB = L >= 4096 ? 1 : 4096 / L;
+  static constexpr int WGPTS = 16384;  // points per workgroup (4 quads per wave at 256 threads)
+  static constexpr int TPB = L >= WGPTS ? 1 : WGPTS / L;
   static constexpr int PTS = TPB * L;
   static constexpr int NW = NT / 64;
   static constexpr int NCOL = PTS / 16;
@@ -143,37 +147,68 @@ __device__ __forceinline__ int row_pos_t(int col, int row) {
   return tau * L + hi * 16 * P + row * P + lo;
 }
 
+// Twiddles of a stage whose 4 tiles sit at consecutive low indices r0 + t:
+// W^{(4g+j)(r0+t)} = W^{(4g+j) r0} * W^{(4g+j) t}.  The second factor depends
+// only on (g, j, t) and is loaded once per stage; the first is one lookup per
+// row and quad.  `mul` maps the exponent onto the table W_L^m.
+struct TwB {
+  float2 b[4][3];  // [j][t-1] = W^{(4g+j) t}
+};
+__device__ __forceinline__ TwB load_twb(const float2* tw, int g, int mul) {
+  TwB B;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int t = 1; t < 4; ++t) B.b[j][t - 1] = tw[(4 * g + j) * t * mul];
+  return B;
+}
+
 // Radix-R0 stage on the vector ALU, HBM -> LDS (always the first stage).
 template <class G, bool SPLIT>
 __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, int valid,
                                              int64_t g0) {
   constexpr int L = G::L, R0 = G::R0, P0 = G::P0;
   uint32_t* ldsl = lds + G::PTS;
+  // W_L^{k t}, k < R0, t < 4: the same for every column quad
+  float2 bt[R0][4];
+#pragma unroll
+  for (int k = 1; k < R0; ++k)
+#pragma unroll
+    for (int t = 1; t < 4; ++t) bt[k][t] = kp.tw[k * t];
   for (int cq = threadIdx.x; cq < G::NCQ0; cq += G::NT) {
     const int col0 = 4 * cq;
     const int tau = col0 / P0;
     const int lo0 = col0 % P0;
-    float2 v[4][R0];
+    // lines past the end of the batch read line 0 of the tile (never stored)
+    const int taul = tau < valid ? tau : 0;
+    u4 hh[R0], ll[R0];
 #pragma unroll
     for (int d = 0; d < R0; ++d) {
-      const int p = tau * L + d * P0 + lo0;
-      u4 h = {0, 0, 0, 0}, l = {0, 0, 0, 0};
-      if (tau < valid) {
-        h = gld4(kp.in + g0 + p);
-        if constexpr (SPLIT) l = gld4(kp.in + kp.in_plane + g0 + p);
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) v[t][d] = value<SPLIT>(h[t], l[t]);
+      const int p = taul * L + d * P0 + lo0;
+      hh[d] = gld4(kp.in + g0 + p);
+      if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + g0 + p);
+      else ll[d] = u4{0, 0, 0, 0};
     }
+    float2 a[R0];
+#pragma unroll
+    for (int k = 1; k < R0; ++k) {
+      a[k] = kp.tw[k * lo0];  // W_L^{k lo0}, k lo0 < L
+      a[k].x *= kp.r0scale;
+      a[k].y *= kp.r0scale;
+    }
+    float2 v[4][R0];
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t][d] = value<SPLIT>(hh[d][t], ll[d][t]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       small_dft<R0>(v[t], kp.sgn);
-      const int lo = lo0 + t;
+      v[t][0].x *= kp.r0scale;
+      v[t][0].y *= kp.r0scale;
 #pragma unroll
-      for (int k = 0; k < R0; ++k) {
-        float2 w = kp.tw[k * lo];  // W_L^{k * lo}, k * lo < L
-        w.x *= kp.r0scale;
-        w.y *= kp.r0scale;
+      for (int k = 1; k < R0; ++k) {
+        const float2 w = t == 0 ? a[k] : cmul(a[k], bt[k][t]);  // W_L^{k (lo0 + t)}
         v[t][k] = cmul(v[t][k], w);
       }
     }
@@ -196,13 +231,17 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
 
 // Radix-16 stage with digit stride P.  SRCG: read HBM (first stage), else LDS.
 // P > 1: writes LDS (twiddled); P == 1: last stage, writes HBM in natural order.
+// Loads of a stage (data, then twiddles) are all issued before the first use.
 template <class G, int P, bool SRCG, bool SPLIT>
 __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, int valid,
                                             int64_t g0, const FOps& f) {
   constexpr int L = G::L, R0 = G::R0, S = G::S;
+  constexpr int TM = P > 1 ? L / (16 * P) : 1;  // W_{16P}^e = W_L^{e TM}
   uint32_t* ldsl = lds + G::PTS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
+  TwB B;
+  if constexpr (P > 1) B = load_twb(kp.tw, g, TM);
 #pragma unroll
   for (int qq = 0; qq < G::QPW; ++qq) {
     const int Q = wave * G::QPW + qq;
@@ -210,45 +249,50 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
     u4 xh[4], xl[4];  // xh[t] = rows 4g..4g+3 of tile t
     if constexpr (P > 1) {
       // tiles along the contiguous low index: one 16-byte access per row
+      u4 rh[4], rl[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int p = row_pos_t<L, P>(col0, 4 * g + i);
-        u4 h = {0, 0, 0, 0}, l = {0, 0, 0, 0};
+        int p = row_pos_t<L, P>(col0, 4 * g + i);
         if constexpr (SRCG) {
-          if (p / L < valid) {
-            h = gld4(kp.in + g0 + p);
-            if constexpr (SPLIT) l = gld4(kp.in + kp.in_plane + g0 + p);
-          }
+          if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
+          rh[i] = gld4(kp.in + g0 + p);
+          if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + g0 + p);
         } else {
-          h = lds_ld4(lds, p);
-          if constexpr (SPLIT) l = lds_ld4(ldsl, p);
+          rh[i] = lds_ld4(lds, p);
+          if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, p);
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          xh[t][i] = h[t];
-          xl[t][i] = l[t];
-        }
+        if constexpr (!SPLIT) rl[i] = u4{0, 0, 0, 0};
       }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xh[t][i] = rh[i][t];
+          xl[t][i] = rl[i][t];
+        }
     } else {
       // last stage: rows are contiguous; columns enumerate natural order
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int col = col0 + t;
-        const int tau = col / (L / 16);
+        int tau = col / (L / 16);
+        if constexpr (SRCG && G::TPB > 1) tau = tau < valid ? tau : 0;
         const int p = tau * L + posrev_hi<R0, S>(col % (L / 16)) * 16 + 4 * g;
-        u4 h = {0, 0, 0, 0}, l = {0, 0, 0, 0};
         if constexpr (SRCG) {
-          if (tau < valid) {
-            h = gld4(kp.in + g0 + p);
-            if constexpr (SPLIT) l = gld4(kp.in + kp.in_plane + g0 + p);
-          }
+          xh[t] = gld4(kp.in + g0 + p);
+          if constexpr (SPLIT) xl[t] = gld4(kp.in + kp.in_plane + g0 + p);
         } else {
-          h = lds_ld4(lds, p);
-          if constexpr (SPLIT) l = lds_ld4(ldsl, p);
+          xh[t] = lds_ld4(lds, p);
+          if constexpr (SPLIT) xl[t] = lds_ld4(ldsl, p);
         }
-        xh[t] = h;
-        xl[t] = l;
+        if constexpr (!SPLIT) xl[t] = u4{0, 0, 0, 0};
       }
+    }
+    float2 a[4];  // W_{16P}^{(4g+j) r0}
+    if constexpr (P > 1) {
+      const int r0 = col0 % P;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = kp.tw[(4 * g + j) * r0 * TM];
     }
     uint32_t oh[4][4], ol[4][4];  // [t][j]
 #pragma unroll
@@ -257,34 +301,26 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
       dft_tile<SPLIT>(xh[t], xl[t], f, yr, yi);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float re = yr[j], im = yi[j];
-        if constexpr (P > 1) {
-          const int lo = (col0 + t) % P;
-          const int row = 4 * g + j;
-          const float2 w = kp.tw[row * lo * (L / (16 * P))];  // W_{16P}^{row * lo}
-          const float2 z = cmul(make_float2(re, im), w);
-          re = z.x;
-          im = z.y;
-        }
-        emit<SPLIT>(re, im, oh[t][j], ol[t][j]);
+        float2 z = make_float2(yr[j], yi[j]);
+        if constexpr (P > 1) z = cmul(z, t == 0 ? a[j] : cmul(a[j], B.b[j][t - 1]));
+        uint32_t eh = 0, el = 0;
+        emit<SPLIT>(z.x, z.y, eh, el);
+        oh[t][j] = eh;
+        ol[t][j] = el;
       }
     }
     if constexpr (P > 1) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = row_pos_t<L, P>(col0, 4 * g + j);
-        u4 h = {oh[0][j], oh[1][j], oh[2][j], oh[3][j]};
-        lds_st4(lds, p, h);
-        if constexpr (SPLIT) {
-          u4 l = {ol[0][j], ol[1][j], ol[2][j], ol[3][j]};
-          lds_st4(ldsl, p, l);
-        }
+        lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+        if constexpr (SPLIT) lds_st4(ldsl, p, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
       }
     } else {
       // natural output index of (row, col): tau*L + klow + (L/16)*row
       if constexpr (L / 16 >= 4) {
         const int tau = col0 / (L / 16);
-        if (tau < valid) {
+        if (G::TPB == 1 || tau < valid) {
           const int klow0 = col0 % (L / 16);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -391,20 +427,27 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
     const int col0 = 4 * cq;
     const int c = col0 % C;
     const int lo = col0 / C;  // in [0, P0)
-    float2 v[4][R0];
+    u4 hh[R0], ll[R0];
 #pragma unroll
     for (int d = 0; d < R0; ++d) {
       const int64_t a = cx.in_base + (int64_t)(d * P0 + lo) * kp.s_in + c;
-      u4 h = gld4(kp.in + a), l = {0, 0, 0, 0};
-      if constexpr (SPLIT) l = gld4(kp.in + kp.in_plane + a);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) v[t][d] = value<SPLIT>(h[t], l[t]);
+      hh[d] = gld4(kp.in + a);
+      if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + a);
+      else ll[d] = u4{0, 0, 0, 0};
     }
+    float2 wt[R0];
+#pragma unroll
+    for (int k = 0; k < R0; ++k) wt[k] = kp.tw[k * lo];
+    float2 v[4][R0];
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t][d] = value<SPLIT>(hh[d][t], ll[d][t]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) small_dft<R0>(v[t], kp.sgn);
 #pragma unroll
     for (int k = 0; k < R0; ++k) {
-      float2 w = kp.tw[k * lo];
+      float2 w = wt[k];
       w.x *= kp.r0scale;
       w.y *= kp.r0scale;
       u4 h, l;
@@ -444,41 +487,67 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
     const int col0 = 4 * c16 + 64 * Q;
     const int c = col0 % C;
     const int rest = col0 / C;
-    const bool active = rest < L / 16;  // masks idle lanes of tiny tiles
+    // idle lanes of tiny tiles (fewer than 64 columns) read column block 0
+    constexpr bool kFull = G::NCOL >= 64 * G::NQ;
+    const bool active = kFull || rest < L / 16;
+    const int restl = active ? rest : 0;
     int lo = 0, jb = 0;
     if constexpr (P > 1) {
-      lo = rest % P;
-      jb = (rest / P) * 16 * P + lo;  // j = jb + row * P
+      lo = restl % P;
+      jb = (restl / P) * 16 * P + lo;  // j = jb + row * P
     } else {
-      jb = posrev_hi<R0, S>(rest) * 16;  // j = jb + row
+      jb = posrev_hi<R0, S>(restl) * 16;  // j = jb + row
     }
-    u4 xh[4], xl[4];
+    u4 rh[4], rl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = jb + (4 * g + i) * P;
-      u4 h = {0, 0, 0, 0}, l = {0, 0, 0, 0};
-      if (active) {
-        if constexpr (SRCG) {
-          const int64_t a = cx.in_base + (int64_t)j * kp.s_in + c;
-          h = gld4(kp.in + a);
-          if constexpr (SPLIT) l = gld4(kp.in + kp.in_plane + a);
+      if constexpr (SRCG) {
+        const int64_t a = cx.in_base + (int64_t)j * kp.s_in + c;
+        rh[i] = gld4(kp.in + a);
+        if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + a);
+      } else {
+        rh[i] = lds_ld4(lds, j * C + c);
+        if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, j * C + c);
+      }
+      if constexpr (!SPLIT) rl[i] = u4{0, 0, 0, 0};
+    }
+    // twiddles: the 4 tiles share (row, lo), hence one per row.  The extra
+    // inter-pass twiddle W_M^{ci k} depends on the column ci too: with
+    // ci = ci0 + t it is W_M^{ci0 k} * (W_M^k)^t (three lookups per row).
+    float2 w[4][4];  // [t][j]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (P > 1) {
+        const float2 v = kp.tw[(4 * g + j) * lo * (L / (16 * P))];  // W_{16P}^{row lo}
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t][j] = v;
+      } else if constexpr (XTW) {
+        const int64_t k = restl + (L / 16) * (4 * g + j);  // natural output index
+        if (kp.xdiv == 1) {
+          const float2 a = xtwiddle(kp, cx.i0 + c, k);
+          const float2 b1 = kp.xtw_lo[k];  // W_M^k (k < L <= 2^xbits)
+          const float2 b2 = cmul(b1, b1);
+          w[0][j] = a;
+          w[1][j] = cmul(a, b1);
+          w[2][j] = cmul(a, b2);
+          w[3][j] = cmul(a, cmul(b2, b1));
         } else {
-          h = lds_ld4(lds, j * C + c);
-          if constexpr (SPLIT) l = lds_ld4(ldsl, j * C + c);
+          const float2 a = xtwiddle(kp, (cx.i0 + c) / kp.xdiv, k);  // same column group
+#pragma unroll
+          for (int t = 0; t < 4; ++t) w[t][j] = a;
         }
       }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        xh[t][i] = h[t];
-        xl[t][i] = l[t];
-      }
     }
-    uint32_t oh[4][4], ol[4][4];  // [t][j]
-    // the 4 tiles share (row, lo), hence one twiddle per row
-    float2 w[4];
+    u4 xh[4], xl[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      w[j] = P > 1 ? kp.tw[(4 * g + j) * lo * (L / (16 * P))] : make_float2(1.f, 0.f);
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        xh[t][i] = rh[i][t];
+        xl[t][i] = rl[i][t];
+      }
+    uint32_t oh[4][4], ol[4][4];  // [t][j]
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       f4 yr, yi;
@@ -486,14 +555,11 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float2 z = make_float2(yr[j], yi[j]);
-        const int row = 4 * g + j;
-        if constexpr (P > 1) {
-          z = cmul(z, w[j]);  // W_{16P}^{row * lo}
-        } else if constexpr (XTW) {
-          const int64_t k = rest + (L / 16) * row;  // natural output index
-          z = cmul(z, xtwiddle(kp, (cx.i0 + c + t) / kp.xdiv, k));
-        }
-        emit<SPLIT>(z.x, z.y, oh[t][j], ol[t][j]);
+        if constexpr (P > 1 || XTW) z = cmul(z, w[t][j]);
+        uint32_t eh = 0, el = 0;
+        emit<SPLIT>(z.x, z.y, eh, el);
+        oh[t][j] = eh;
+        ol[t][j] = el;
       }
     }
     if constexpr (P > 1 || TSTORE) {
@@ -521,22 +587,23 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
   if constexpr (P == 1 && TSTORE) {
     __syncthreads();
     // transposed store: column c of the tile becomes a row of L natural-order
-    // outputs; output k sits at position posrev_hi(k mod L/16) * 16 + k / (L/16)
-    for (int task = threadIdx.x; task < C * (L / 4); task += G::NT) {
-      const int c = task / (L / 4);
-      const int k0 = 4 * (task % (L / 4));
-      u4 h, l;
+    // outputs; output k sits at position posrev_hi(k mod L/16) * 16 + k / (L/16).
+    // Each task reads 4 adjacent columns of one output (16 bytes of LDS) and
+    // writes them to 4 rows; adjacent lanes take adjacent k, so every store
+    // instruction writes 256 contiguous bytes of a row.
+    for (int task = threadIdx.x; task < (C / 4) * L; task += G::NT) {
+      const int c4 = 4 * (task / L);
+      const int k = task % L;
+      const int j = posrev_hi<R0, S>(k % (L / 16)) * 16 + k / (L / 16);
+      const u4 h = lds_ld4(lds, j * C + c4);
+      u4 l = {0, 0, 0, 0};
+      if constexpr (SPLIT) l = lds_ld4(ldsl, j * C + c4);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + i;
-        const int j = posrev_hi<R0, S>(k % (L / 16)) * 16 + k / (L / 16);
-        h[i] = lds_ld1(lds, j * C + c);
-        l[i] = 0;
-        if constexpr (SPLIT) l[i] = lds_ld1(ldsl, j * C + c);
+      for (int t = 0; t < 4; ++t) {
+        const int64_t a = cx.out_base + (int64_t)(c4 + t) * L + k;
+        kp.out[a] = h[t];
+        if constexpr (SPLIT) kp.out[kp.out_plane + a] = l[t];
       }
-      const int64_t a = cx.out_base + (int64_t)c * L + k0;
-      gst4(kp.out + a, h);
-      if constexpr (SPLIT) gst4(kp.out + kp.out_plane + a, l);
     }
   }
 }
@@ -723,7 +790,7 @@ size_t kernel_lds_bytes(const KernelKey& k) {
 }
 
 int64_t kernel_points_per_wg(const KernelKey& k) {
-  if (k.kind == K_ROW) return k.L >= 4096 ? k.L : 4096;
+  if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
   return (int64_t)k.L * k.C;
 }
 

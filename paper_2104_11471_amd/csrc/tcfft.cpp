@@ -400,7 +400,8 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
       launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
       if (sp.xmod > 0) {
         const int lg = ilog2(sp.xmod);
-        dpp.xbits = (lg + 1) / 2;
+        // the lo table also serves W_M^k for every output index k < L
+        dpp.xbits = std::max((lg + 1) / 2, ilog2(sp.key.L));
         const int64_t nlo = (int64_t)1 << dpp.xbits, nhi = sp.xmod >> dpp.xbits;
         if ((st = dev_alloc(p, (size_t)nlo * sizeof(float2), &t))) break;
         dpp.xtw_lo = (float2*)t;
