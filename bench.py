@@ -54,6 +54,23 @@ def time_launches(fn, reps: int, stream) -> float:
     return start.elapsed_time(end) / 1e3 / reps
 
 
+def measured_traffic(kernel_name: str):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3
+    counter summary, or None when the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2104_11471_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernels_sha256_16"):
+        return None
+    k = rec["per_launch_kib"].get(kernel_name)
+    if not k:
+        return None
+    return int(round((k["fetch"] * rec["fetch_factor"] + k["write"] * rec["write_factor"]) * 1024))
+
+
 def accuracy_sample(plan, x_dev, y_dev, x_host, tones, rng, nsample=32):
     """Relative L2 of sampled transforms (random rows + every tone row) vs the oracle."""
     import oracle
@@ -183,11 +200,14 @@ def main():
     single = [n for n in SIZES if plans[n].num_launches == 1] or list(SIZES)
     dom = max(single, key=lambda n: per[n]["us"])
     dom_bytes = 8.0 * TOTAL_POINTS
-    dom_kernel = plans[dom].describe()["passes"][0]
+    dk = plans[dom].describe()["passes"][0]
+    kname = (f"row_kernel<{dk['L']}, {dk['radices'][0] if dk['radices'][0] != 16 else 1}, "
+             f"{dk['NT']}, false>")
     achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"row_kernel<L={dom_kernel['L']}> N={dom} batch={TOTAL_POINTS // dom}"}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
+                "kernel": f"{kname} N={dom} batch={TOTAL_POINTS // dom}",
+                "alg_bytes_per_launch": int(dom_bytes)}
 
     comparator = None
     if not args.no_comparator:

@@ -1,0 +1,138 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/tcfft.h declares, validates arguments, plans without a device
+and reports the absence of a device -- no compute calls."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tcfft.h")
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2104_11471_amd import tcfft
+    return tcfft
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree(tc):
+    assert declared_functions() == sorted(tc.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(tc):
+    lib = ctypes.CDLL(tc.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(tc):
+    for s in range(7):
+        assert tc.lib.tcfft_status_string(s)
+    assert b"tcfft" in tc.lib.tcfft_version()
+
+
+@pytest.mark.parametrize("dims,batch,dirn,prec,flags,status", [
+    ((12,), 1, -1, 0, 0, 2),          # not a power of two
+    ((8,), 1, -1, 0, 0, 2),           # below 16
+    ((1 << 28,), 1, -1, 0, 0, 2),     # above 2^27
+    ((256,), 0, -1, 0, 0, 1),         # batch <= 0
+    ((256,), 1, 0, 0, 0, 1),          # bad direction
+    ((256,), 1, -1, 7, 0, 1),         # bad precision
+    ((256,), 1, -1, 0, 64, 1),        # unknown flag
+    ((4096, 64), 1, -1, 0, 0, 2),     # 2D first dim above 2048
+    ((64, 64), 1, -1, 2, 0, 2),       # FP32 comparator is 1D only
+    ((1 << 20,), 4096, -1, 0, 0, 2),  # more than 2^31 points per plan
+])
+def test_dry_run_rejects(tc, dims, batch, dirn, prec, flags, status):
+    with pytest.raises(tc.TcfftError) as e:
+        tc.dry_run(dims, batch, dirn, prec, flags)
+    assert e.value.status == status
+
+
+def _radices(p):
+    r = 1
+    for x in p["radices"]:
+        r *= x
+    return r
+
+
+@pytest.mark.parametrize("lg", range(4, 28))
+def test_plan_factorises_every_1d_size(tc, lg):
+    n = 1 << lg
+    d = tc.dry_run((n,), 1)
+    prod = 1
+    for p in d["passes"]:
+        assert _radices(p) == p["L"]
+        prod *= p["L"]
+        assert p["lds"] <= 160 * 1024
+        assert set(p["radices"]) <= {2, 4, 8, 16}
+        assert p["radices"].count(16) == len(p["radices"]) - (p["radices"][0] != 16)
+    assert prod == n
+    # static scale: 2 per radix-16 stage, 1 for radix 2/4, 2 for radix 8
+    s = sum(2 * p["radices"].count(16) + {1: 0, 2: 1, 4: 1, 8: 2}[
+        p["radices"][0] if p["radices"][0] != 16 else 1] for p in d["passes"])
+    assert d["scale_log2"] == s
+    assert len(d["passes"]) == (1 if n <= 16384 else (2 if n <= (1 << 22) else 3))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("dims", [(16, 16), (256, 256), (512, 512), (1024, 1024), (2048, 64),
+                                  (128, 16384)])
+def test_plan_2d(tc, dims, prec):
+    d = tc.dry_run(dims, 2, precision=prec)
+    assert [p["kernel"] for p in d["passes"]] == ["row", "col"]
+    assert d["passes"][0]["L"] == dims[1] and d["passes"][1]["L"] == dims[0]
+    for p in d["passes"]:
+        assert p["lds"] <= 160 * 1024
+    assert d["buffer_bytes"] == 2 * dims[0] * dims[1] * (4 if prec == "fp16" else 8)
+
+
+def test_multi_pass_layout(tc):
+    d = tc.dry_run((1 << 20,), 4)
+    p1, p2 = d["passes"]
+    assert p1["xtw"] == 1 and p1["tstore"] == 1 and p1["dst"] == 2   # to workspace
+    assert p2["xtw"] == 0 and p2["src"] == 2 and p2["dst"] == 1
+    assert d["workspace_bytes"] == d["buffer_bytes"]
+    d3 = tc.dry_run((1 << 24,), 1)
+    assert [p["xtw"] for p in d3["passes"]] == [1, 1, 0]
+    assert [(p["src"], p["dst"]) for p in d3["passes"]] == [(0, 2), (2, 1), (1, 1)]
+
+
+def test_no_scale_flag(tc):
+    assert tc.dry_run((256,), 1, flags=tc.FLAG_NO_SCALE)["scale_log2"] == 0
+    assert tc.dry_run((256,), 1)["scale_log2"] == 4
+
+
+def test_plan_create_without_device(tc):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(tc.TcfftError) as e:
+        tc.Plan((256,), 4)
+    assert e.value.status == 3  # TCFFT_ERR_NO_DEVICE
+
+
+def test_null_arguments(tc):
+    lib = tc.lib
+    assert lib.tcfft_exec(None, None, None, None) == 1
+    assert lib.tcfft_plan_destroy(None) == 0
+    assert lib.tcfft_plan_scale_log2(None) == -1
+    assert lib.tcfft_plan_buffer_bytes(None) == 0
+    assert lib.tcfft_plan_num_launches(None) == -1
+    assert lib.tcfft_exec_many(None, None, None, -1, None) == 1
+    assert lib.tcfft_exec_many(None, None, None, 0, None) == 0
+    h = ctypes.c_void_p()
+    assert lib.tcfft_plan_create(ctypes.byref(h), 3, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
+    assert lib.tcfft_plan_create(None, 1, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
