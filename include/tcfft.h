@@ -65,7 +65,8 @@ enum {
 
 enum {
   TCFFT_FLAG_NO_SCALE = 1u, /* S = 0: literally unnormalised (may overflow FP16 for large N) */
-  TCFFT_FLAG_NO_GRAPH = 2u  /* reserved: never capture the pass sequence in a HIP graph */
+  TCFFT_FLAG_NO_GRAPH = 2u, /* reserved: never capture the pass sequence in a HIP graph */
+  TCFFT_FLAG_TUNE = 4u      /* time every planner candidate on the device and keep the fastest */
 };
 
 /*
@@ -80,8 +81,10 @@ enum {
  *   precision  TCFFT_PREC_*
  *   flags      TCFFT_FLAG_* bit set
  * Allocates the plan's device tables (DFT-matrix operands, twiddles generated
- * in FP64 on the device) and its workspace on the current device; the call
- * synchronises the current device before returning.
+ * in FP64 on the device) and its workspace on the current device; the tables
+ * are generated on a private stream that the call waits for (other streams
+ * are not synchronised).  With TCFFT_FLAG_TUNE, or when the tuning cache holds
+ * a choice for this key, the planner's knobs come from the autotuner.
  * Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, ALLOC, LAUNCH.
  */
 tcfft_status tcfft_plan_create(tcfft_plan* out, int rank, const int64_t* dims, int64_t batch,
@@ -103,9 +106,16 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream);
 
 /*
- * Executes several plans in order on one stream: job j runs plans[j] on
- * (in[j], out[j]).  Each job's result equals tcfft_exec of that job alone.
- * Errors: as tcfft_exec; INVALID_ARG for njobs < 0 or null arrays.
+ * Mixed-size batch execution: job j runs plans[j] on (in[j], out[j]), all jobs
+ * enqueued on one stream.  Jobs of any sizes and precisions mix.  Pass l of
+ * every job runs after pass l-1 of every job; within a pass level, one
+ * persistent launch per kernel variant serves every job of that variant (a
+ * device-resident descriptor table lists the jobs and their workgroup
+ * ranges), so a batch of hundreds of uneven transforms costs a handful of
+ * launches.  Each job's result is bitwise equal to tcfft_exec of that job
+ * alone.  Jobs must not share a plan (workspace) or an output buffer.
+ * Errors: as tcfft_exec; INVALID_ARG for njobs < 0 or null arrays; ALLOC
+ * when the descriptor table cannot be allocated (stream-ordered).
  */
 tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
                              int njobs, void* stream);
@@ -140,6 +150,100 @@ int tcfft_plan_describe(tcfft_plan plan, char* buf, size_t len);
  */
 int tcfft_plan_dry_run(int rank, const int64_t* dims, int64_t batch, int dir, int precision,
                        unsigned flags, char* buf, size_t len);
+
+/*
+ * Autotuner (plan "wisdom").  A plan created with TCFFT_FLAG_TUNE times every
+ * candidate the planner can build for its (rank, dims, batch rounded down to a
+ * power of two, precision) -- threads per workgroup, column-block width,
+ * factorisation of long lengths -- on scratch device buffers and keeps the
+ * fastest; the choice is cached in-process and reused by later plans with the
+ * same key (tuned or not).
+ *   tcfft_tune_candidates  JSON array of the candidate plans (no device);
+ *                          returns the needed length or -(status).
+ *   tcfft_tune_cache_size  number of cached choices.
+ *   tcfft_tune_cache_save  writes the cache as text; INVALID_ARG if the file
+ *                          cannot be written.
+ *   tcfft_tune_cache_load  merges a saved cache; INVALID_ARG on a bad file.
+ *   tcfft_tune_cache_clear forgets every cached choice.
+ */
+int tcfft_tune_candidates(int rank, const int64_t* dims, int64_t batch, int precision, char* buf,
+                          size_t len);
+int tcfft_tune_cache_size(void);
+tcfft_status tcfft_tune_cache_save(const char* path);
+tcfft_status tcfft_tune_cache_load(const char* path);
+void tcfft_tune_cache_clear(void);
+
+/*
+ * Serving: continuous batching of mixed-size requests (not a paper item; the
+ * scheduler feeds tcfft_exec_many-style grouped launches).
+ *
+ * A server owns `nslots` slots; a slot is a HIP stream, an event and a device
+ * workspace arena of `arena_bytes` (0 = mem_budget_bytes / nslots).  Requests
+ * are queued FIFO.  Whenever a slot is idle, the scheduler thread admits the
+ * longest queue prefix (at most max_batch_jobs requests) whose bytes -- input
+ * + output payload + workspace of every request in flight -- stay within
+ * mem_budget_bytes and whose workspaces fit the slot's arena, and launches it
+ * as one grouped execution; batches in different slots overlap on the GPU.
+ * Completion is detected by polling the slot events; each request gets
+ * submit / start / done timestamps (steady clock, ns, see tcfft_server_now_ns).
+ * Plans are created per shape on first use (or ahead of time with
+ * tcfft_server_prepare) and shared by all slots.  Each result is bitwise the
+ * result of tcfft_exec of the same request alone (same kernels).
+ */
+typedef struct tcfft_server_s* tcfft_server;
+
+typedef struct {
+  int nslots;              /* 1..16 concurrent batches (HIP streams) */
+  int max_batch_jobs;      /* >= 1 requests per batch */
+  size_t mem_budget_bytes; /* > 0: payload + workspace of all requests in flight */
+  size_t arena_bytes;      /* workspace arena per slot; 0 = mem_budget_bytes / nslots */
+} tcfft_server_config;
+
+typedef struct {
+  int rank;             /* 1 or 2 */
+  int64_t dims[2];      /* {N, ignored} or {nx, ny} */
+  int64_t batch;        /* transforms in this request */
+  int dir;              /* TCFFT_FORWARD / TCFFT_INVERSE */
+  int precision;        /* TCFFT_PREC_FP16 or TCFFT_PREC_SPLIT_FP16 */
+  const void* in;       /* device buffers in the layouts of tcfft_exec, 16-byte aligned, */
+  void* out;            /* owned by the caller and untouched by it until completion */
+  uint64_t tag;         /* returned in the completion record */
+} tcfft_request;
+
+typedef struct {
+  uint64_t tag;
+  int status;           /* tcfft_status of the request */
+  int batch_jobs;       /* requests in the batch that carried it */
+  int64_t t_submit_ns, t_start_ns, t_done_ns;
+  int batch_id;
+} tcfft_completion;
+
+typedef struct {
+  int64_t submitted, completed, rejected, batches, max_batch_jobs;
+  int64_t max_inflight_bytes, inflight_bytes, queued, plans;
+} tcfft_server_stats;
+
+/* Creates a server on the current device and starts its scheduler thread.
+ * Errors: INVALID_ARG (bad config), NO_DEVICE, ALLOC (streams/arenas). */
+tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* cfg);
+/* Creates the plans of these request shapes now (buffers are not used). */
+tcfft_status tcfft_server_prepare(tcfft_server s, const tcfft_request* reqs, int n);
+/* Enqueues a request (thread-safe, non-blocking).  Errors: INVALID_ARG,
+ * UNSUPPORTED (size), ALLOC (the request alone exceeds the budget or an
+ * arena: it could never be admitted). */
+tcfft_status tcfft_server_submit(tcfft_server s, const tcfft_request* req);
+/* Moves up to `max` completion records into `out`; returns how many, or
+ * -(status) on bad arguments. */
+int tcfft_server_poll(tcfft_server s, tcfft_completion* out, int max);
+/* Waits until nothing is queued or in flight (timeout_ms < 0: forever);
+ * INTERNAL on timeout. */
+tcfft_status tcfft_server_wait_idle(tcfft_server s, int64_t timeout_ms);
+tcfft_status tcfft_server_get_stats(tcfft_server s, tcfft_server_stats* st);
+/* Stops the scheduler (queued, unadmitted requests are dropped), waits for
+ * in-flight batches and frees everything.  NULL is accepted. */
+tcfft_status tcfft_server_destroy(tcfft_server s);
+/* The steady clock of the timestamps, in ns. */
+int64_t tcfft_server_now_ns(void);
 
 /* Static text for a status code. */
 const char* tcfft_status_string(tcfft_status s);

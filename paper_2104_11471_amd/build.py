@@ -19,7 +19,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
-UNITS = ["kernels.hip", "tcfft.cpp"]
+UNITS = ["k_row.hip", "k_col_small.hip", "k_col_256.hip", "k_col_large.hip", "k_misc.hip",
+         "registry.cpp", "tcfft.cpp", "serve.cpp"]
 
 
 def _hipcc() -> str:

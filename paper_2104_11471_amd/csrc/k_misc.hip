@@ -1,0 +1,89 @@
+// FP32 radix-2 comparator and FP64 table generators.
+#include "common.h"
+#include "kernels.h"
+
+namespace tcfft {
+
+// ===========================================================================
+// FP32 radix-2 Stockham comparator: one launch per stage, 16 B/point each way.
+// ===========================================================================
+__global__ __launch_bounds__(256) void radix2_stage_kernel(const float2* __restrict__ in,
+                                                           float2* __restrict__ out, int64_t n,
+                                                           int64_t ns, int64_t total,
+                                                           const float2* __restrict__ tw) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= total) return;
+  const int64_t half = n >> 1;
+  const int64_t b = gid / half, j = gid - b * half;
+  const float2* x = in + b * n;
+  float2* y = out + b * n;
+  const int64_t k = j & (ns - 1);
+  const float2 a = x[j];
+  const float2 c = cmul(x[j + half], tw[k * (n / (2 * ns))]);  // W_{2ns}^k
+  const int64_t o = ((j - k) << 1) + k;
+  y[o] = make_float2(a.x + c.x, a.y + c.y);
+  y[o + ns] = make_float2(a.x - c.x, a.y - c.y);
+}
+
+void launch_radix2_stage(const float2* in, float2* out, int64_t n, int64_t ns, int64_t batch,
+                         const float2* tw, hipStream_t s) {
+  const int64_t total = batch * (n / 2);
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(radix2_stage_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, ns,
+                     total, tw);
+}
+
+// ===========================================================================
+// FP64 table generation on the device.
+// ===========================================================================
+__global__ void gen_twiddles_kernel(float2* tw, int64_t count, int64_t modulus, int64_t mult,
+                                    double sgn) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= count) return;
+  const int64_t e = (int64_t)(((unsigned __int128)m * (unsigned __int128)mult) % (unsigned __int128)modulus);
+  double sn, cs;
+  sincospi(2.0 * (double)e / (double)modulus, &sn, &cs);
+  tw[m] = make_float2((float)cs, (float)(sgn * sn));
+}
+
+void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mult, double sgn,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(gen_twiddles_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     tw, count, modulus, mult, sgn);
+}
+
+__global__ void gen_fimg_kernel(h8* img, double sgn, double scale) {
+  const int lane = threadIdx.x;  // 64 lanes
+  const int g = lane >> 4, m = lane & 15;
+  h8 rh, ih, rl, il;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 4 * g + i;
+    const int e = (m * r) & 15;
+    double sn, cs;
+    sincospi(2.0 * (double)e / 16.0, &sn, &cs);
+    const double fr = cs * scale, fi = sgn * sn * scale;
+    // Yr row: [Fr, -Fi]; Yi row: [Fi, Fr]  (pairs = re/im halves of input row r)
+    const double vr[2] = {fr, -fi}, vi[2] = {fi, fr};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      _Float16 a = (_Float16)vr[h];
+      _Float16 b = (_Float16)vi[h];
+      rh[2 * i + h] = a;
+      ih[2 * i + h] = b;
+      rl[2 * i + h] = (_Float16)((vr[h] - (double)a) * 2048.0);
+      il[2 * i + h] = (_Float16)((vi[h] - (double)b) * 2048.0);
+    }
+  }
+  img[lane] = rh;
+  img[64 + lane] = ih;
+  img[128 + lane] = rl;
+  img[192 + lane] = il;
+}
+
+void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<h8*>(img), sgn,
+                     scale);
+}
+
+}  // namespace tcfft

@@ -30,6 +30,11 @@ struct KParams {
   int64_t xdiv;
 };
 
+// The same struct is read by host code (x86-64) and, in grouped launches, by
+// device code from a table in device memory: both ABIs lay it out alike
+// (8-byte pointers and int64_t, 4-byte float/int32, natural alignment).
+static_assert(sizeof(KParams) == 152, "KParams layout changed: host and device must agree");
+
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
 enum KernelKind { K_ROW = 0, K_COL = 1 };
@@ -46,8 +51,22 @@ struct KernelKey {
 };
 
 typedef void (*KernelFn)(KParams);
+// Grouped launch: (descriptor table, prefix of workgroups per job, job count).
+typedef void (*MultiFn)(const KParams*, const int64_t*, int);
 
-// Returns the kernel for `key`, or nullptr when that variant is not compiled.
+struct KernelFns {
+  KernelFn single = nullptr;
+  MultiFn multi = nullptr;
+};
+
+// Looks up the compiled variant for `key`; false when it is not compiled.
+bool find_kernels(const KernelKey& key, KernelFns* out);
+// Per translation unit lookups (row kernels, column kernels by length range).
+bool find_row_kernels(const KernelKey& key, KernelFns* out);
+bool find_col_kernels_small(const KernelKey& key, KernelFns* out);
+bool find_col_kernels_256(const KernelKey& key, KernelFns* out);
+bool find_col_kernels_large(const KernelKey& key, KernelFns* out);
+// Returns the single-launch kernel for `key`, or nullptr.
 KernelFn find_kernel(const KernelKey& key);
 // Dynamic LDS bytes the kernel needs.
 size_t kernel_lds_bytes(const KernelKey& key);

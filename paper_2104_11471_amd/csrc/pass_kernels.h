@@ -25,6 +25,7 @@
 //                  and the passes of long 1D transforms).  Optional extra
 //                  inter-pass twiddle and transposed store for the four-step
 //                  long transforms.
+#pragma once
 #include "common.h"
 #include "kernels.h"
 
@@ -371,11 +372,11 @@ __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds
   }
 }
 
+// One workgroup's share of a row pass: workgroup index wg of the pass.
 template <int L, int R0, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
+__device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = RowGeom<L, R0, NT>;
-  extern __shared__ uint32_t lds[];
-  const int64_t t0 = (int64_t)blockIdx.x * G::TPB;
+  const int64_t t0 = wg * G::TPB;
   const int64_t rem = kp.ntrans - t0;
   const int valid = rem < G::TPB ? (int)rem : G::TPB;
   const int64_t g0 = t0 * L;
@@ -391,6 +392,12 @@ __global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
       row_stages_from<G, G::S - 2, SPLIT>(kp, lds, valid, g0, f);
     }
   }
+}
+
+template <int L, int R0, int NT, bool SPLIT>
+__global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
+  extern __shared__ uint32_t lds[];
+  row_body<L, R0, NT, SPLIT>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -618,14 +625,13 @@ __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds
   }
 }
 
+// One workgroup's share of a column pass: workgroup index wg of the pass.
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
-__global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
+__device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = ColGeom<L, R0, C, NT>;
-  extern __shared__ uint32_t lds[];
   ColCtx cx;
-  const int64_t w = blockIdx.x;
-  cx.outer = w / kp.blocks;
-  cx.i0 = (w % kp.blocks) * C;
+  cx.outer = wg / kp.blocks;
+  cx.i0 = (wg % kp.blocks) * C;
   cx.in_base = cx.outer * kp.in_outer + cx.i0;
   if constexpr (TSTORE)
     cx.out_base = cx.outer * kp.out_outer + cx.i0 * L;
@@ -645,153 +651,55 @@ __global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
   }
 }
 
-// ===========================================================================
-// FP32 radix-2 Stockham comparator: one launch per stage, 16 B/point each way.
-// ===========================================================================
-__global__ __launch_bounds__(256) void radix2_stage_kernel(const float2* __restrict__ in,
-                                                           float2* __restrict__ out, int64_t n,
-                                                           int64_t ns, int64_t total,
-                                                           const float2* __restrict__ tw) {
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= total) return;
-  const int64_t half = n >> 1;
-  const int64_t b = gid / half, j = gid - b * half;
-  const float2* x = in + b * n;
-  float2* y = out + b * n;
-  const int64_t k = j & (ns - 1);
-  const float2 a = x[j];
-  const float2 c = cmul(x[j + half], tw[k * (n / (2 * ns))]);  // W_{2ns}^k
-  const int64_t o = ((j - k) << 1) + k;
-  y[o] = make_float2(a.x + c.x, a.y + c.y);
-  y[o + ns] = make_float2(a.x - c.x, a.y - c.y);
-}
-
-void launch_radix2_stage(const float2* in, float2* out, int64_t n, int64_t ns, int64_t batch,
-                         const float2* tw, hipStream_t s) {
-  const int64_t total = batch * (n / 2);
-  const int64_t blocks = (total + 255) / 256;
-  hipLaunchKernelGGL(radix2_stage_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, ns,
-                     total, tw);
+template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
+__global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
+  extern __shared__ uint32_t lds[];
+  col_body<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================
-// FP64 table generation on the device.
+// Grouped mixed-size launch: one launch runs the same pass kernel for many
+// jobs (different sizes of batch, buffers, tables).  Job j owns workgroup
+// indices [prefix[j], prefix[j+1]); the descriptor table and the prefix array
+// live in device memory, so a captured launch can be replayed with new jobs.
+// The grid is persistent: each workgroup strides over the job tiles.
 // ===========================================================================
-__global__ void gen_twiddles_kernel(float2* tw, int64_t count, int64_t modulus, int64_t mult,
-                                    double sgn) {
-  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (m >= count) return;
-  const int64_t e = (int64_t)(((unsigned __int128)m * (unsigned __int128)mult) % (unsigned __int128)modulus);
-  double sn, cs;
-  sincospi(2.0 * (double)e / (double)modulus, &sn, &cs);
-  tw[m] = make_float2((float)cs, (float)(sgn * sn));
-}
-
-void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mult, double sgn,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(gen_twiddles_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
-                     tw, count, modulus, mult, sgn);
-}
-
-__global__ void gen_fimg_kernel(h8* img, double sgn, double scale) {
-  const int lane = threadIdx.x;  // 64 lanes
-  const int g = lane >> 4, m = lane & 15;
-  h8 rh, ih, rl, il;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 4 * g + i;
-    const int e = (m * r) & 15;
-    double sn, cs;
-    sincospi(2.0 * (double)e / 16.0, &sn, &cs);
-    const double fr = cs * scale, fi = sgn * sn * scale;
-    // Yr row: [Fr, -Fi]; Yi row: [Fi, Fr]  (pairs = re/im halves of input row r)
-    const double vr[2] = {fr, -fi}, vi[2] = {fi, fr};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      _Float16 a = (_Float16)vr[h];
-      _Float16 b = (_Float16)vi[h];
-      rh[2 * i + h] = a;
-      ih[2 * i + h] = b;
-      rl[2 * i + h] = (_Float16)((vr[h] - (double)a) * 2048.0);
-      il[2 * i + h] = (_Float16)((vi[h] - (double)b) * 2048.0);
-    }
+__device__ __forceinline__ int find_job(const int64_t* __restrict__ prefix, int njobs, int64_t w) {
+  int lo = 0, hi = njobs - 1;  // largest j with prefix[j] <= w
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= w) lo = mid;
+    else hi = mid - 1;
   }
-  img[lane] = rh;
-  img[64 + lane] = ih;
-  img[128 + lane] = rl;
-  img[192 + lane] = il;
+  return lo;
 }
 
-void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s) {
-  hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<h8*>(img), sgn,
-                     scale);
+template <int L, int R0, int NT, bool SPLIT>
+__global__ __launch_bounds__(NT) void row_kernel_multi(const KParams* __restrict__ jobs,
+                                                       const int64_t* __restrict__ prefix,
+                                                       int njobs) {
+  extern __shared__ uint32_t lds[];
+  const int64_t total = prefix[njobs];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int j = find_job(prefix, njobs, w);
+    const KParams kp = jobs[j];
+    row_body<L, R0, NT, SPLIT>(kp, w - prefix[j], lds);
+    __syncthreads();  // the next tile's first stage rewrites LDS
+  }
 }
 
-// ===========================================================================
-// Variant registry.
-// ===========================================================================
-#define ROWK(L_, R_, N_)                                                                \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_)                         \
-    return k.split ? (KernelFn)row_kernel<L_, R_, N_, true> : (KernelFn)row_kernel<L_, R_, N_, false>;
-
-#define COLK4(L_, R_, C_, N_, X_, T_)                                                   \
-  if (k.kind == K_COL && k.L == L_ && k.R0 == R_ && k.C == C_ && k.NT == N_ &&          \
-      k.xtw == X_ && k.tstore == T_)                                                    \
-    return k.split ? (KernelFn)col_kernel<L_, R_, C_, N_, true, X_, T_>                 \
-                   : (KernelFn)col_kernel<L_, R_, C_, N_, false, X_, T_>;
-#define COLK(L_, R_, C_, N_)                                                            \
-  COLK4(L_, R_, C_, N_, false, false) COLK4(L_, R_, C_, N_, true, false)                \
-  COLK4(L_, R_, C_, N_, true, true)
-
-KernelFn find_kernel(const KernelKey& k) {
-  ROWK(16, 1, 256)
-  ROWK(32, 2, 256)
-  ROWK(64, 4, 256)
-  ROWK(128, 8, 256)
-  ROWK(256, 1, 256)
-  ROWK(512, 2, 256)
-  ROWK(1024, 4, 256)
-  ROWK(2048, 8, 256)
-  ROWK(4096, 1, 256)
-  ROWK(8192, 2, 256)
-  ROWK(16384, 4, 256)
-  ROWK(8192, 2, 512)
-  ROWK(16384, 4, 512)
-  // column kernels: L * C <= 32768 points (128 KB FP16)
-  COLK(16, 1, 64, 64)
-  COLK(32, 2, 64, 128)
-  COLK(64, 4, 64, 256)
-  COLK(128, 8, 64, 256)
-  COLK(256, 1, 64, 256)
-  COLK(256, 1, 32, 256)
-  COLK(512, 2, 32, 256)
-  COLK(512, 2, 64, 256)
-  COLK(1024, 4, 32, 256)
-  COLK(1024, 4, 16, 256)
-  COLK(2048, 8, 16, 256)
-  COLK(512, 2, 16, 256)
-  COLK(2048, 8, 8, 256)
-  // narrow blocks for small inner sizes (2D with ny = 16 or 32)
-  COLK(16, 1, 16, 64)
-  COLK(32, 2, 16, 64)
-  COLK(64, 4, 16, 64)
-  COLK(128, 8, 16, 128)
-  COLK(256, 1, 16, 256)
-  COLK(16, 1, 32, 64)
-  COLK(32, 2, 32, 64)
-  COLK(64, 4, 32, 128)
-  COLK(128, 8, 32, 256)
-  return nullptr;
-}
-
-size_t kernel_lds_bytes(const KernelKey& k) {
-  const int64_t pts = kernel_points_per_wg(k);
-  return (size_t)pts * 4 * (k.split ? 2 : 1);
-}
-
-int64_t kernel_points_per_wg(const KernelKey& k) {
-  if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
-  return (int64_t)k.L * k.C;
+template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
+__global__ __launch_bounds__(NT) void col_kernel_multi(const KParams* __restrict__ jobs,
+                                                       const int64_t* __restrict__ prefix,
+                                                       int njobs) {
+  extern __shared__ uint32_t lds[];
+  const int64_t total = prefix[njobs];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int j = find_job(prefix, njobs, w);
+    const KParams kp = jobs[j];
+    col_body<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, w - prefix[j], lds);
+    __syncthreads();
+  }
 }
 
 }  // namespace tcfft

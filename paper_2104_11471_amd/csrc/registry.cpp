@@ -1,0 +1,26 @@
+// Variant registry and per-variant sizes.
+#include "kernels.h"
+
+namespace tcfft {
+
+bool find_kernels(const KernelKey& k, KernelFns* out) {
+  return find_row_kernels(k, out) || find_col_kernels_small(k, out) ||
+         find_col_kernels_256(k, out) || find_col_kernels_large(k, out);
+}
+
+KernelFn find_kernel(const KernelKey& k) {
+  KernelFns f;
+  return find_kernels(k, &f) ? f.single : nullptr;
+}
+
+size_t kernel_lds_bytes(const KernelKey& k) {
+  const int64_t pts = kernel_points_per_wg(k);
+  return (size_t)pts * 4 * (k.split ? 2 : 1);
+}
+
+int64_t kernel_points_per_wg(const KernelKey& k) {
+  if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
+  return (int64_t)k.L * k.C;
+}
+
+}  // namespace tcfft

@@ -1,0 +1,365 @@
+// Serving scheduler: continuous batching of FFT requests of mixed sizes.
+//
+// Requests arrive on any thread (tcfft_server_submit) into a FIFO queue.  One
+// scheduler thread owns `nslots` slots; a slot is a HIP stream, a completion
+// event and a device workspace arena.  Whenever a slot is idle and requests
+// are queued, the scheduler admits the longest FIFO prefix that fits the
+// memory budget (payload in + out + workspace of every request in flight) and
+// the slot's arena, and launches it as one grouped mixed-size execution
+// (tcfft_internal_exec_jobs): so requests that arrive while others run on the
+// GPU join the next batch as soon as a slot and memory free up, and batches in
+// different slots overlap on the device.  The scheduler polls the slots'
+// events and timestamps each request's completion.
+//
+// Plans are shared by all slots and hold only read-only device tables (DFT
+// operands, twiddles); workspaces come from the slot arenas, so any number of
+// jobs of one shape may be in flight at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "runtime.h"
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Req {
+  tcfft_request r;
+  int64_t t_submit = 0;
+  size_t payload = 0;  // in + out bytes
+  size_t ws = 0;       // workspace bytes
+  tcfft_plan plan = nullptr;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  void* arena = nullptr;
+  size_t arena_cap = 0;
+  bool busy = false;
+  std::vector<Req> reqs;
+  size_t bytes = 0;
+  int64_t t_start = 0;
+  int batch_id = 0;
+};
+
+typedef std::tuple<int, int64_t, int64_t, int, int> PlanKey;  // rank, nx, ny, dir, prec
+
+}  // namespace
+
+struct tcfft_server_s {
+  tcfft_server_config cfg{};
+  int device = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;  // queue, plans, counters
+  std::condition_variable cv;
+  std::deque<Req> queue;
+  std::map<PlanKey, tcfft_plan> plans;
+  std::mutex done_mu;
+  std::deque<tcfft_completion> done;
+  size_t inflight = 0;  // bytes of admitted, unfinished requests
+  tcfft_server_stats stats{};
+  int next_batch = 0;
+  std::atomic<bool> stop{false};
+  std::atomic<int> busy_slots{0};
+  std::thread worker;
+};
+
+namespace {
+
+// Looks up (or creates) the shared plan of a request shape.  Plans are built
+// with batch 1: jobs run any batch with an external workspace.
+tcfft_status get_plan(tcfft_server_s* s, const tcfft_request& r, tcfft_plan* out) {
+  PlanKey key{r.rank, r.dims[0], r.rank == 2 ? r.dims[1] : 1, r.dir, r.precision};
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->plans.find(key);
+    if (it != s->plans.end()) {
+      *out = it->second;
+      return TCFFT_OK;
+    }
+  }
+  tcfft_plan p = nullptr;
+  tcfft_status st = tcfft_plan_create(&p, r.rank, r.dims, 1, r.dir, r.precision, 0);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto ins = s->plans.emplace(key, p);
+  if (!ins.second) {  // another thread won the race
+    tcfft_plan_destroy(p);
+    p = ins.first->second;
+  }
+  *out = p;
+  return TCFFT_OK;
+}
+
+void complete(tcfft_server_s* s, const Slot& sl, int status, int64_t t_done) {
+  std::lock_guard<std::mutex> lk(s->done_mu);
+  for (const Req& q : sl.reqs) {
+    tcfft_completion c{};
+    c.tag = q.r.tag;
+    c.status = status;
+    c.t_submit_ns = q.t_submit;
+    c.t_start_ns = sl.t_start;
+    c.t_done_ns = t_done;
+    c.batch_id = sl.batch_id;
+    c.batch_jobs = (int)sl.reqs.size();
+    s->done.push_back(c);
+  }
+}
+
+// Retires finished slots; returns true when any finished.
+bool reap(tcfft_server_s* s) {
+  bool any = false;
+  for (Slot& sl : s->slots) {
+    if (!sl.busy) continue;
+    const hipError_t e = hipEventQuery(sl.ev);
+    if (e == hipErrorNotReady) continue;
+    const int64_t t = now_ns();
+    complete(s, sl, e == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH, t);
+    if (e != hipSuccess) (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->inflight -= sl.bytes;
+      s->stats.completed += (int64_t)sl.reqs.size();
+    }
+    sl.busy = false;
+    sl.reqs.clear();
+    sl.bytes = 0;
+    s->busy_slots.fetch_sub(1);
+    any = true;
+  }
+  return any;
+}
+
+// Admits a FIFO prefix of the queue into idle slot `sl` and launches it.
+bool dispatch(tcfft_server_s* s, Slot& sl) {
+  std::vector<Req> batch;
+  size_t bytes = 0, arena_used = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while (!s->queue.empty() && (int)batch.size() < s->cfg.max_batch_jobs) {
+      const Req& q = s->queue.front();
+      const size_t need = q.payload + q.ws;
+      if (s->inflight + bytes + need > s->cfg.mem_budget_bytes) break;
+      if (arena_used + align_up(q.ws) > sl.arena_cap) break;
+      bytes += need;
+      arena_used += align_up(q.ws);
+      batch.push_back(q);
+      s->queue.pop_front();
+    }
+    if (batch.empty()) return false;
+    s->inflight += bytes;
+    s->stats.max_inflight_bytes = std::max<int64_t>(s->stats.max_inflight_bytes, (int64_t)s->inflight);
+    s->stats.batches += 1;
+    s->stats.max_batch_jobs = std::max<int64_t>(s->stats.max_batch_jobs, (int64_t)batch.size());
+  }
+  std::vector<tcfft::Job> jobs(batch.size());
+  size_t off = 0;
+  for (size_t i = 0; i < batch.size(); ++i) {
+    const Req& q = batch[i];
+    void* ws = q.ws ? (void*)((uint8_t*)sl.arena + off) : nullptr;
+    off += align_up(q.ws);
+    jobs[i] = tcfft::Job{q.plan, q.r.in, q.r.out, q.r.batch, ws};
+  }
+  sl.reqs = std::move(batch);
+  sl.bytes = bytes;
+  sl.t_start = now_ns();
+  sl.batch_id = s->next_batch++;
+  tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), sl.stream);
+  if (st == TCFFT_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = TCFFT_ERR_LAUNCH;
+  if (st != TCFFT_OK) {
+    (void)hipGetLastError();
+    complete(s, sl, st, now_ns());
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->inflight -= sl.bytes;
+    s->stats.completed += (int64_t)sl.reqs.size();
+    sl.reqs.clear();
+    sl.bytes = 0;
+    return true;
+  }
+  sl.busy = true;
+  s->busy_slots.fetch_add(1);
+  return true;
+}
+
+void run(tcfft_server_s* s) {
+  (void)hipSetDevice(s->device);
+  while (!s->stop.load()) {
+    bool progressed = reap(s);
+    for (Slot& sl : s->slots)
+      if (!sl.busy && dispatch(s, sl)) progressed = true;
+    if (progressed) continue;
+    if (s->busy_slots.load() > 0) {
+      std::this_thread::yield();  // poll the in-flight slots' events
+    } else {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait_for(lk, std::chrono::microseconds(200),
+                     [s] { return !s->queue.empty() || s->stop.load(); });
+    }
+  }
+}
+
+tcfft_status request_sizes(tcfft_server_s* s, const tcfft_request& r, Req* q) {
+  if (r.rank != 1 && r.rank != 2) return TCFFT_ERR_INVALID_ARG;
+  if (r.batch <= 0 || !r.in || !r.out) return TCFFT_ERR_INVALID_ARG;
+  if ((((uintptr_t)r.in) & 15) || (((uintptr_t)r.out) & 15)) return TCFFT_ERR_INVALID_ARG;
+  if (r.precision == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  tcfft_status st = get_plan(s, r, &q->plan);
+  if (st) return st;
+  int64_t dims[2] = {r.dims[0], r.rank == 2 ? r.dims[1] : 1};
+  char buf[16];
+  // validate the batch against the plan limits with the planner itself
+  const int n = tcfft_plan_dry_run(r.rank, dims, r.batch, r.dir, r.precision, 0, buf, sizeof buf);
+  if (n < 0) return (tcfft_status)(-n);
+  const int64_t pts = tcfft_internal_plan_points(q->plan) * r.batch;
+  const size_t elt = r.precision == TCFFT_PREC_SPLIT_FP16 ? 8 : 4;
+  q->payload = 2 * (size_t)pts * elt;
+  q->ws = tcfft_internal_plan_ws_bytes(q->plan, r.batch);
+  return TCFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t tcfft_server_now_ns(void) { return now_ns(); }
+
+tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* cfg) {
+  if (!out || !cfg) return TCFFT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (cfg->nslots < 1 || cfg->nslots > 16 || cfg->max_batch_jobs < 1 || cfg->mem_budget_bytes == 0)
+    return TCFFT_ERR_INVALID_ARG;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_NO_DEVICE;
+  }
+  tcfft_server_s* s = new tcfft_server_s();
+  s->cfg = *cfg;
+  (void)hipGetDevice(&s->device);
+  s->slots.resize(cfg->nslots);
+  // each slot's arena may hold the workspace of a full budget's worth of jobs
+  const size_t arena = align_up(cfg->arena_bytes ? cfg->arena_bytes : cfg->mem_budget_bytes / cfg->nslots);
+  for (Slot& sl : s->slots) {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&sl.arena, arena) != hipSuccess) {
+      (void)hipGetLastError();
+      for (Slot& t : s->slots) {
+        if (t.arena) (void)hipFree(t.arena);
+        if (t.ev) (void)hipEventDestroy(t.ev);
+        if (t.stream) (void)hipStreamDestroy(t.stream);
+      }
+      delete s;
+      return TCFFT_ERR_ALLOC;
+    }
+    sl.arena_cap = arena;
+  }
+  s->worker = std::thread(run, s);
+  *out = s;
+  return TCFFT_OK;
+}
+
+tcfft_status tcfft_server_prepare(tcfft_server s, const tcfft_request* reqs, int n) {
+  if (!s || n < 0 || (n > 0 && !reqs)) return TCFFT_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    tcfft_plan p = nullptr;
+    tcfft_status st = get_plan(s, reqs[i], &p);
+    if (st) return st;
+  }
+  return TCFFT_OK;
+}
+
+tcfft_status tcfft_server_submit(tcfft_server s, const tcfft_request* req) {
+  if (!s || !req) return TCFFT_ERR_INVALID_ARG;
+  Req q;
+  q.r = *req;
+  q.t_submit = now_ns();
+  tcfft_status st = request_sizes(s, *req, &q);
+  if (st == TCFFT_OK) {
+    // a request that can never fit the budget or an arena is refused outright
+    if (q.payload + q.ws > s->cfg.mem_budget_bytes || align_up(q.ws) > s->slots[0].arena_cap)
+      st = TCFFT_ERR_ALLOC;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (st != TCFFT_OK) {
+    s->stats.rejected += 1;
+    return st;
+  }
+  s->queue.push_back(q);
+  s->stats.submitted += 1;
+  s->cv.notify_one();
+  return TCFFT_OK;
+}
+
+int tcfft_server_poll(tcfft_server s, tcfft_completion* out, int max) {
+  if (!s || !out || max < 0) return -(int)TCFFT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->done_mu);
+  int n = 0;
+  while (n < max && !s->done.empty()) {
+    out[n++] = s->done.front();
+    s->done.pop_front();
+  }
+  return n;
+}
+
+tcfft_status tcfft_server_wait_idle(tcfft_server s, int64_t timeout_ms) {
+  if (!s) return TCFFT_ERR_INVALID_ARG;
+  const int64_t deadline = now_ns() + timeout_ms * 1000000;
+  while (true) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->queue.empty() && s->inflight == 0 && s->busy_slots.load() == 0) return TCFFT_OK;
+    }
+    if (timeout_ms >= 0 && now_ns() > deadline) return TCFFT_ERR_INTERNAL;
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+}
+
+tcfft_status tcfft_server_get_stats(tcfft_server s, tcfft_server_stats* st) {
+  if (!s || !st) return TCFFT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *st = s->stats;
+  st->inflight_bytes = (int64_t)s->inflight;
+  st->queued = (int64_t)s->queue.size();
+  st->plans = (int64_t)s->plans.size();
+  return TCFFT_OK;
+}
+
+tcfft_status tcfft_server_destroy(tcfft_server s) {
+  if (!s) return TCFFT_OK;
+  s->stop.store(true);
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+  }
+  for (Slot& sl : s->slots) {
+    if (sl.arena) (void)hipFree(sl.arena);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  for (auto& kv : s->plans) tcfft_plan_destroy(kv.second);
+  delete s;
+  return TCFFT_OK;
+}
+
+}  // extern "C"

@@ -13,12 +13,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/tcfft.h"
 #include "kernels.h"
+#include "runtime.h"
 
 using namespace tcfft;
 
@@ -51,7 +53,9 @@ struct PassSpec {
   int64_t grid = 0;
   size_t lds = 0;
   // geometry
-  int64_t ntrans = 0;  // row kernel
+  int64_t ntrans = 0;  // row kernel: lines of the whole plan
+  int64_t lines_per_batch = 0;  // row kernel: lines per transform of the batch
+  int64_t tpb = 1;     // row kernel: lines per workgroup
   int64_t s_in = 0, s_out = 0, blocks = 0, in_outer = 0, out_outer = 0, q = 1, qstride = 0;
   // extra twiddle
   int64_t xmod = 0, xdiv = 1;
@@ -69,8 +73,19 @@ struct Desc {
   unsigned flags = 0;
 };
 
+// Tunable planner knobs (the autotuner sweeps these).
+struct Choice {
+  int row_nt = 256;  // threads per workgroup of row passes (256, or 512 where compiled)
+  int cmax = 64;     // widest column block a column pass may use
+  int nf = 0;        // 0: default factorisation of long 1D lengths; else pass lengths f[]
+  int f[3] = {0, 0, 0};
+};
+
 struct PlanSpec {
   Desc d;
+  Choice ch;
+  bool tuned = false;
+  double tuned_us = 0.0;
   int64_t npts = 0;  // points per transform
   std::vector<PassSpec> passes;
   int scale = 0;
@@ -78,9 +93,10 @@ struct PlanSpec {
   size_t buf_bytes = 0;
 };
 
-tcfft_status col_choice(int L, int64_t inner, bool split, bool xtw, bool tstore, KernelKey* out) {
+tcfft_status col_choice(int L, int64_t inner, int cmax, bool split, bool xtw, bool tstore,
+                        KernelKey* out) {
   for (int C : {64, 32, 16, 8}) {
-    if (C > inner) continue;
+    if (C > inner || C > cmax) continue;
     for (int NT : {256, 128, 64}) {
       KernelKey k{K_COL, L, r0_of(L), C, NT, split ? 1 : 0, xtw ? 1 : 0, tstore ? 1 : 0};
       if (find_kernel(k) && kernel_lds_bytes(k) <= kMaxLds) {
@@ -92,20 +108,26 @@ tcfft_status col_choice(int L, int64_t inner, bool split, bool xtw, bool tstore,
   return TCFFT_ERR_UNSUPPORTED;
 }
 
-tcfft_status row_choice(int L, bool split, KernelKey* out) {
-  KernelKey k{K_ROW, L, r0_of(L), 0, 256, split ? 1 : 0, 0, 0};
-  if (!find_kernel(k) || kernel_lds_bytes(k) > kMaxLds) return TCFFT_ERR_UNSUPPORTED;
-  *out = k;
-  return TCFFT_OK;
+tcfft_status row_choice(int L, int nt, bool split, KernelKey* out) {
+  for (int NT : {nt, 256}) {
+    KernelKey k{K_ROW, L, r0_of(L), 0, NT, split ? 1 : 0, 0, 0};
+    if (find_kernel(k) && kernel_lds_bytes(k) <= kMaxLds) {
+      *out = k;
+      return TCFFT_OK;
+    }
+  }
+  return TCFFT_ERR_UNSUPPORTED;
 }
 
 // Row pass over `lines` contiguous lines of L points.
 tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst) {
   PassSpec p;
-  tcfft_status st = row_choice(L, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key);
+  tcfft_status st = row_choice(L, ps.ch.row_nt, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key);
   if (st) return st;
   const int64_t tpb = kernel_points_per_wg(p.key) / L;
+  p.tpb = tpb;
   p.ntrans = lines;
+  p.lines_per_batch = lines / ps.d.batch;
   p.grid = (lines + tpb - 1) / tpb;
   p.lds = kernel_lds_bytes(p.key);
   p.src = src;
@@ -119,10 +141,14 @@ tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst) 
 // o*in_outer + j*inner + i.  Output per mode (see KParams).
 tcfft_status add_col_pass(PlanSpec& ps, int L, int64_t inner, int64_t outer, int64_t in_outer,
                           int64_t out_outer, int64_t s_out, int64_t q, int64_t qstride,
-                          bool tstore, int64_t xmod, int64_t xdiv, int src, int dst) {
+                          bool tstore, int64_t xmod, int64_t xdiv, int src, int dst,
+                          int64_t cgroup = 0) {
   PassSpec p;
   const bool xtw = xmod > 0;
-  tcfft_status st = col_choice(L, inner, ps.d.prec == TCFFT_PREC_SPLIT_FP16, xtw, tstore, &p.key);
+  // a column block must not straddle a group of `cgroup` columns (3-pass pass 2)
+  const int cmax = (int)std::min<int64_t>(ps.ch.cmax, cgroup > 0 ? cgroup : ps.ch.cmax);
+  tcfft_status st =
+      col_choice(L, inner, cmax, ps.d.prec == TCFFT_PREC_SPLIT_FP16, xtw, tstore, &p.key);
   if (st) return st;
   p.s_in = inner;
   p.s_out = s_out;
@@ -164,7 +190,8 @@ tcfft_status validate(const Desc& d) {
   if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
   if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
   if (d.prec < 0 || d.prec > 2) return TCFFT_ERR_INVALID_ARG;
-  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH)) return TCFFT_ERR_INVALID_ARG;
+  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE))
+    return TCFFT_ERR_INVALID_ARG;
   if (d.nx <= 0 || d.ny <= 0) return TCFFT_ERR_INVALID_ARG;
   if (!is_pow2(d.nx) || !is_pow2(d.ny)) return TCFFT_ERR_UNSUPPORTED;
   if (d.rank == 1) {
@@ -178,11 +205,12 @@ tcfft_status validate(const Desc& d) {
   return TCFFT_OK;
 }
 
-tcfft_status build_spec(const Desc& d, PlanSpec* out) {
+tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
   tcfft_status st = validate(d);
   if (st) return st;
   PlanSpec ps;
   ps.d = d;
+  ps.ch = ch;
   ps.npts = d.nx * d.ny;
   const int64_t B = d.batch;
   const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
@@ -199,6 +227,15 @@ tcfft_status build_spec(const Desc& d, PlanSpec* out) {
       st = add_row_pass(ps, (int)N, B, 0, 1);
     } else {
       std::vector<int> f = long_split(N);
+      if (ch.nf > 0) {
+        int64_t prod = 1;
+        f.assign(ch.f, ch.f + ch.nf);
+        for (int v : f) {
+          if (v < 16 || v > kMaxColL || !is_pow2(v)) return TCFFT_ERR_UNSUPPORTED;
+          prod *= v;
+        }
+        if (prod != N) return TCFFT_ERR_UNSUPPORTED;
+      }
       if (f.size() == 2) {
         const int64_t N1 = f[0], N2 = f[1];
         // pass 1: N1-point DFTs over n1 (stride N2), twiddle W_N^{n2 k1},
@@ -214,7 +251,8 @@ tcfft_status build_spec(const Desc& d, PlanSpec* out) {
         // pass 2: over n2 (stride N3 N1), twiddle W_{N2 N3}^{n3 k2}, store
         // Z2[n3][k2][k1] (into the output buffer)
         if (!st)
-          st = add_col_pass(ps, (int)N2, N3 * N1, B, N, N, N1, N1, N2 * N1, false, N2 * N3, N1, 2, 1);
+          st = add_col_pass(ps, (int)N2, N3 * N1, B, N, N, N1, N1, N2 * N1, false, N2 * N3, N1, 2, 1,
+                            N1);
         // pass 3: over n3 (stride N2 N1) -> X[k3 N1 N2 + k2 N1 + k1], in place
         if (!st)
           st = add_col_pass(ps, (int)N3, N2 * N1, B, N, N, N2 * N1, N2 * N1, 0, false, 0, 1, 1, 1);
@@ -241,14 +279,18 @@ tcfft_status build_spec(const Desc& d, PlanSpec* out) {
 
 std::string describe(const PlanSpec& ps) {
   static const char* precs[] = {"fp16", "split_fp16", "fp32_radix2"};
-  char b[512];
+  char b[1024];
   std::string s;
   std::snprintf(b, sizeof b,
                 "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
-                "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,\"passes\":[",
+                "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,"
+                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d]},\"tuned\":%s,"
+                "\"tuned_us\":%.2f,\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
                 ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
-                precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes);
+                precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes, ps.ch.row_nt, ps.ch.cmax,
+                ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
+                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.tuned ? "true" : "false", ps.tuned_us);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
@@ -294,11 +336,12 @@ int copy_out(const std::string& s, char* buf, size_t len) {
 // Device side of a plan.
 struct DevPass {
   PassSpec spec;
-  KernelFn fn = nullptr;
+  KernelFns fn;
   float2* tw = nullptr;      // W_L^m
   float2* xtw_lo = nullptr;  // two-level W_M tables
   float2* xtw_hi = nullptr;
   int xbits = 0;
+  int persist_grid = 0;      // resident workgroups for the grouped (persistent) launch
 };
 
 }  // namespace
@@ -335,7 +378,7 @@ void free_plan(tcfft_plan_s* p) {
   delete p;
 }
 
-tcfft_status check_device(int* dev) {
+tcfft_status check_device(int* dev, int* ncu) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
     (void)hipGetLastError();
@@ -345,34 +388,39 @@ tcfft_status check_device(int* dev) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return TCFFT_ERR_NO_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TCFFT_ERR_NO_DEVICE;
+  if (ncu) *ncu = prop.multiProcessorCount;
   return TCFFT_OK;
 }
 
 std::mutex g_attr_mu;
 
-tcfft_status prepare_kernel(KernelFn fn, size_t lds) {
+tcfft_status prepare_kernel(const void* fn, size_t lds) {
   if (lds <= 65536) return TCFFT_OK;
   std::lock_guard<std::mutex> lk(g_attr_mu);
-  if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess) {
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     (void)hipGetLastError();
     return TCFFT_ERR_LAUNCH;
   }
   return TCFFT_OK;
 }
 
-tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
-  PlanSpec ps;
-  tcfft_status st = build_spec(d, &ps);
-  if (st) return st;
-  int dev = 0;
-  st = check_device(&dev);
+// Builds the device tables of a plan from its spec.  Table generation runs on
+// a private stream so that plan creation never waits on other streams' work.
+tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
+  int dev = 0, ncu = 256;
+  tcfft_status st = check_device(&dev, &ncu);
   if (st) return st;
   tcfft_plan_s* p = new tcfft_plan_s();
   p->spec = ps;
   p->device = dev;
+  const Desc& d = ps.d;
   const double sgn = (double)d.dir;
   hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return TCFFT_ERR_LAUNCH;
+  }
   do {
     if (d.prec == TCFFT_PREC_FP32_RADIX2) {
       void* t = nullptr;
@@ -388,12 +436,20 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
     for (const PassSpec& sp : ps.passes) {
       DevPass dpp;
       dpp.spec = sp;
-      dpp.fn = find_kernel(sp.key);
-      if (!dpp.fn) {
+      if (!find_kernels(sp.key, &dpp.fn)) {
         st = TCFFT_ERR_INTERNAL;
         break;
       }
-      if ((st = prepare_kernel(dpp.fn, sp.lds))) break;
+      if ((st = prepare_kernel((const void*)dpp.fn.single, sp.lds))) break;
+      if ((st = prepare_kernel((const void*)dpp.fn.multi, sp.lds))) break;
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)dpp.fn.multi,
+                                                      sp.key.NT, sp.lds) != hipSuccess ||
+          per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 1;
+      }
+      dpp.persist_grid = per_cu * ncu;
       void* t = nullptr;
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
@@ -402,7 +458,7 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
         const int lg = ilog2(sp.xmod);
         // the lo table also serves W_M^k for every output index k < L
         dpp.xbits = std::max((lg + 1) / 2, ilog2(sp.key.L));
-        const int64_t nlo = (int64_t)1 << dpp.xbits, nhi = sp.xmod >> dpp.xbits;
+        const int64_t nlo = (int64_t)1 << dpp.xbits, nhi = std::max<int64_t>(1, sp.xmod >> dpp.xbits);
         if ((st = dev_alloc(p, (size_t)nlo * sizeof(float2), &t))) break;
         dpp.xtw_lo = (float2*)t;
         if ((st = dev_alloc(p, (size_t)nhi * sizeof(float2), &t))) break;
@@ -416,7 +472,8 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
     if ((st = dev_alloc(p, ps.ws_bytes, &p->ws))) break;
   } while (false);
   if (!st && hipGetLastError() != hipSuccess) st = TCFFT_ERR_LAUNCH;
-  if (!st && hipDeviceSynchronize() != hipSuccess) st = TCFFT_ERR_LAUNCH;
+  if (hipStreamSynchronize(s) != hipSuccess && !st) st = TCFFT_ERR_LAUNCH;
+  (void)hipStreamDestroy(s);
   if (st) {
     free_plan(p);
     return st;
@@ -425,65 +482,394 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
   return TCFFT_OK;
 }
 
-tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+// Kernel parameters of one pass for a job of `batch` transforms (<= the plan's
+// batch) with workspace `ws`; *grid receives the pass's workgroup count.
+KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, void* out,
+                     int64_t batch, void* ws, int64_t* grid) {
   const PlanSpec& ps = p->spec;
-  if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
-    const int T = ilog2(ps.npts);
-    const float2* src = (const float2*)in;
-    float2* ws = (float2*)p->ws;
-    float2* o = (float2*)out;
-    for (int st = 0; st < T; ++st) {
-      // the last stage lands in `out`; earlier ones alternate so that no stage
-      // reads and writes the same buffer
-      float2* dst = ((T - 1 - st) % 2 == 0) ? o : ws;
-      if (st == 0 && dst == src) dst = ws;
-      if (st > 0 && dst == src) dst = (dst == o) ? ws : o;
-      launch_radix2_stage(src, dst, ps.npts, (int64_t)1 << st, ps.d.batch, p->r2tw, s);
-      src = dst;
-    }
-    if (src != o)
-      if (hipMemcpyAsync(o, src, ps.buf_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return TCFFT_ERR_LAUNCH;
-    return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
-  }
-  const int64_t plane = ps.npts * ps.d.batch;
+  const PassSpec& sp = dpp.spec;
   const bool split = ps.d.prec == TCFFT_PREC_SPLIT_FP16;
+  const int64_t plane = ps.npts * batch;
+  auto buf = [&](int which) -> uint32_t* {
+    return which == 0 ? (uint32_t*)in : which == 1 ? (uint32_t*)out : (uint32_t*)ws;
+  };
+  KParams kp{};
+  kp.in = buf(sp.src);
+  kp.out = buf(sp.dst);
+  kp.in_plane = split ? plane : 0;
+  kp.out_plane = split ? plane : 0;
+  if (sp.key.kind == K_ROW) {
+    kp.ntrans = sp.lines_per_batch * batch;
+    *grid = (kp.ntrans + sp.tpb - 1) / sp.tpb;
+  } else {
+    kp.ntrans = 0;
+    *grid = sp.blocks * batch;
+  }
+  kp.tw = dpp.tw;
+  kp.fimg = p->fimg;
+  kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
+  if (ps.d.flags & TCFFT_FLAG_NO_SCALE) kp.r0scale = 1.0f;
+  kp.sgn = (float)ps.d.dir;
+  kp.s_in = sp.s_in;
+  kp.s_out = sp.s_out;
+  kp.blocks = sp.blocks;
+  kp.in_outer = sp.in_outer;
+  kp.out_outer = sp.out_outer;
+  kp.q = sp.q;
+  kp.qstride = sp.qstride;
+  kp.xtw_lo = dpp.xtw_lo;
+  kp.xtw_hi = dpp.xtw_hi;
+  kp.xbits = dpp.xbits;
+  kp.xmask = (uint32_t)(sp.xmod > 0 ? sp.xmod - 1 : 0);
+  kp.xdiv = sp.xdiv;
+  return kp;
+}
+
+tcfft_status exec_r2(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  const PlanSpec& ps = p->spec;
+  const int T = ilog2(ps.npts);
+  const float2* src = (const float2*)in;
+  float2* ws = (float2*)p->ws;
+  float2* o = (float2*)out;
+  for (int st = 0; st < T; ++st) {
+    // the last stage lands in `out`; earlier ones alternate so that no stage
+    // reads and writes the same buffer
+    float2* dst = ((T - 1 - st) % 2 == 0) ? o : ws;
+    if (st == 0 && dst == src) dst = ws;
+    if (st > 0 && dst == src) dst = (dst == o) ? ws : o;
+    launch_radix2_stage(src, dst, ps.npts, (int64_t)1 << st, ps.d.batch, p->r2tw, s);
+    src = dst;
+  }
+  if (src != o)
+    if (hipMemcpyAsync(o, src, ps.buf_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return TCFFT_ERR_LAUNCH;
+  return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
+}
+
+tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return exec_r2(p, in, out, s);
   for (const DevPass& dpp : p->dp) {
-    const PassSpec& sp = dpp.spec;
-    auto buf = [&](int which) -> uint32_t* {
-      return which == 0 ? (uint32_t*)in : which == 1 ? (uint32_t*)out : (uint32_t*)p->ws;
-    };
-    KParams kp{};
-    kp.in = buf(sp.src);
-    kp.out = buf(sp.dst);
-    kp.in_plane = split ? plane : 0;
-    kp.out_plane = split ? plane : 0;
-    kp.ntrans = sp.ntrans;
-    kp.tw = dpp.tw;
-    kp.fimg = p->fimg;
-    kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
-    if (ps.d.flags & TCFFT_FLAG_NO_SCALE) kp.r0scale = 1.0f;
-    kp.sgn = (float)ps.d.dir;
-    kp.s_in = sp.s_in;
-    kp.s_out = sp.s_out;
-    kp.blocks = sp.blocks;
-    kp.in_outer = sp.in_outer;
-    kp.out_outer = sp.out_outer;
-    kp.q = sp.q;
-    kp.qstride = sp.qstride;
-    kp.xtw_lo = dpp.xtw_lo;
-    kp.xtw_hi = dpp.xtw_hi;
-    kp.xbits = dpp.xbits;
-    kp.xmask = (uint32_t)(sp.xmod > 0 ? sp.xmod - 1 : 0);
-    kp.xdiv = sp.xdiv;
+    int64_t grid = 0;
+    KParams kp = make_kparams(p, dpp, in, out, p->spec.d.batch, p->ws, &grid);
     void* args[] = {&kp};
-    if (hipLaunchKernel((const void*)dpp.fn, dim3((unsigned)sp.grid), dim3(sp.key.NT), args,
-                        sp.lds, s) != hipSuccess) {
+    if (hipLaunchKernel((const void*)dpp.fn.single, dim3((unsigned)grid),
+                        dim3(dpp.spec.key.NT), args, dpp.spec.lds, s) != hipSuccess) {
       (void)hipGetLastError();
       return TCFFT_ERR_LAUNCH;
     }
   }
   return TCFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Grouped mixed-size execution.  Pass l of every job runs after pass l-1 of
+// every job (stream order), so one launch per (pass level, kernel variant)
+// serves all jobs of that variant: the descriptor table (one KParams per job)
+// and the prefix sum of their workgroup counts go to device memory, and a
+// persistent grid of resident workgroups strides over all their tiles.
+struct KeyLess {
+  bool operator()(const KernelKey& a, const KernelKey& b) const {
+    return std::memcmp(&a, &b, sizeof(KernelKey)) < 0;
+  }
+};
+
+// Pinned staging slots for descriptor uploads.  A slot is reused only after
+// the copy that read it has completed (its event), so the host never rewrites
+// memory an in-flight copy still reads.
+struct StagingSlot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+std::mutex g_stage_mu;
+StagingSlot g_stage[16];
+unsigned g_stage_next = 0;
+
+tcfft_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  StagingSlot& sl = g_stage[g_stage_next++ % 16];
+  if (sl.pending) {
+    if (hipEventSynchronize(sl.ev) != hipSuccess) return TCFFT_ERR_LAUNCH;
+    sl.pending = false;
+  }
+  if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_LAUNCH;
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    sl.host = nullptr;
+    sl.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64 * 1024);
+    if (hipHostMalloc(&sl.host, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      sl.host = nullptr;
+      return TCFFT_ERR_ALLOC;
+    }
+    sl.cap = cap;
+  }
+  std::memcpy(sl.host, src, bytes);
+  if (hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(sl.ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_LAUNCH;
+  }
+  sl.pending = true;
+  return TCFFT_OK;
+}
+
+struct Group {
+  KernelFns fn;
+  int nt = 0;
+  size_t lds = 0;
+  int persist = 0;
+  std::vector<KParams> jobs;
+  std::vector<int64_t> prefix{0};
+};
+
+}  // namespace
+
+tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s) {
+  int levels = 0;
+  for (int j = 0; j < njobs; ++j) {
+    tcfft_plan_s* p = jobs[j].plan;
+    if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2) {
+      tcfft_status st = exec_r2(p, jobs[j].in, jobs[j].out, s);
+      if (st) return st;
+      continue;
+    }
+    levels = std::max(levels, (int)p->dp.size());
+  }
+  for (int lv = 0; lv < levels; ++lv) {
+    std::map<KernelKey, Group, KeyLess> groups;
+    for (int j = 0; j < njobs; ++j) {
+      tcfft_plan_s* p = jobs[j].plan;
+      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || lv >= (int)p->dp.size()) continue;
+      const DevPass& dpp = p->dp[lv];
+      Group& g = groups[dpp.spec.key];
+      g.fn = dpp.fn;
+      g.nt = dpp.spec.key.NT;
+      g.lds = dpp.spec.lds;
+      g.persist = dpp.persist_grid;
+      int64_t grid = 0;
+      g.jobs.push_back(make_kparams(p, dpp, jobs[j].in, jobs[j].out, jobs[j].batch, jobs[j].ws, &grid));
+      g.prefix.push_back(g.prefix.back() + grid);
+    }
+    for (auto& kv : groups) {
+      Group& g = kv.second;
+      const int n = (int)g.jobs.size();
+      const size_t jb = (size_t)n * sizeof(KParams), pb = (size_t)(n + 1) * sizeof(int64_t);
+      void* dmem = nullptr;
+      if (hipMallocAsync(&dmem, jb + pb, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_ALLOC;
+      }
+      std::vector<uint8_t> host(jb + pb);
+      std::memcpy(host.data(), g.jobs.data(), jb);
+      std::memcpy(host.data() + jb, g.prefix.data(), pb);
+      tcfft_status ust = upload(dmem, host.data(), jb + pb, s);
+      if (ust) return ust;
+      const KParams* djobs = (const KParams*)dmem;
+      const int64_t* dprefix = (const int64_t*)((uint8_t*)dmem + jb);
+      const int64_t total = g.prefix.back();
+      const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(total, g.persist));
+      void* args[] = {&djobs, &dprefix, (void*)&n};
+      if (hipLaunchKernel((const void*)g.fn.multi, dim3(grid), dim3(g.nt), args, g.lds, s) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
+      (void)hipFreeAsync(dmem, s);  // stream-ordered: after the launch has run
+    }
+  }
+  return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
+}
+
+size_t tcfft_internal_plan_ws_bytes(const tcfft_plan_s* p, int64_t batch) {
+  const PlanSpec& ps = p->spec;
+  if (ps.ws_bytes == 0) return 0;
+  return (size_t)((double)ps.ws_bytes * (double)batch / (double)ps.d.batch);
+}
+
+int64_t tcfft_internal_plan_batch(const tcfft_plan_s* p) { return p->spec.d.batch; }
+int64_t tcfft_internal_plan_points(const tcfft_plan_s* p) { return p->spec.npts; }
+int tcfft_internal_plan_prec(const tcfft_plan_s* p) { return p->spec.d.prec; }
+
+namespace {
+
+tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void* const* out,
+                            int njobs, hipStream_t s) {
+  std::vector<Job> jobs(njobs);
+  for (int j = 0; j < njobs; ++j)
+    jobs[j] = Job{plans[j], in[j], const_cast<void*>(out[j]), plans[j]->spec.d.batch, plans[j]->ws};
+  return tcfft_internal_exec_jobs(jobs.data(), njobs, s);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner.  For a (rank, size, batch bucket, precision) it times every
+// candidate Choice on scratch buffers (plan creation cost is excluded, as in
+// the paper's measurement, Sec. 5.1) and keeps the fastest.  Results are
+// cached in-process and can be saved/loaded as text ("wisdom").
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<Choice, double>> g_tune;
+
+std::string tune_key(const Desc& d) {
+  char b[160];
+  std::snprintf(b, sizeof b, "r%d_%lldx%lld_b%d_p%d", d.rank, (long long)d.nx, (long long)d.ny,
+                ilog2(d.batch), d.prec);
+  return b;
+}
+
+std::vector<Choice> candidates(const Desc& d) {
+  std::vector<Choice> out;
+  if (d.prec == TCFFT_PREC_FP32_RADIX2) return out;
+  const bool longp = d.rank == 1 && d.nx > kMaxRowL;
+  if (!longp) {
+    for (int nt : {256, 512})
+      for (int cmax : {64, 32, 16}) {
+        if (d.rank == 1 && cmax != 64) continue;
+        Choice c;
+        c.row_nt = nt;
+        c.cmax = cmax;
+        out.push_back(c);
+      }
+    return out;
+  }
+  const int lg = ilog2(d.nx);
+  for (int e1 = 4; e1 <= 11; ++e1) {  // two passes
+    const int e2 = lg - e1;
+    if (e2 < 4 || e2 > 11) continue;
+    for (int cmax : {64, 32}) {
+      Choice c;
+      c.cmax = cmax;
+      c.nf = 2;
+      c.f[0] = 1 << e1;
+      c.f[1] = 1 << e2;
+      out.push_back(c);
+    }
+  }
+  if (lg > 22) {  // three passes
+    std::vector<int> base = long_split(d.nx);
+    if (base.size() == 2) {  // a balanced three-way split as an extra candidate
+      base = {1 << (lg / 3), 1 << ((lg - lg / 3) / 2), 1 << (lg - lg / 3 - (lg - lg / 3) / 2)};
+    }
+    std::sort(base.begin(), base.end());
+    do {
+      if (base.size() != 3 || base[0] < 16 || base[2] > kMaxColL) continue;
+      Choice c;
+      c.nf = 3;
+      for (int i = 0; i < 3; ++i) c.f[i] = base[i];
+      out.push_back(c);
+    } while (std::next_permutation(base.begin(), base.end()));
+  }
+  return out;
+}
+
+tcfft_status time_spec(const PlanSpec& ps, void* a, void* b, double* us) {
+  tcfft_plan_s* p = nullptr;
+  tcfft_status st = create_device_plan(ps, &p);
+  if (st) return st;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return TCFFT_ERR_LAUNCH;
+  }
+  for (int i = 0; i < 2 && !st; ++i) st = exec_impl(p, a, b, s);
+  const int reps = 5;
+  (void)hipEventRecord(e0, s);
+  for (int i = 0; i < reps && !st; ++i) st = exec_impl(p, a, b, s);
+  (void)hipEventRecord(e1, s);
+  float ms = 0.f;
+  if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    st = TCFFT_ERR_LAUNCH;
+  *us = ms * 1e3 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  free_plan(p);
+  return st;
+}
+
+// Picks the Choice for `d`: the cached one, else (when tuning) the fastest
+// candidate, else the defaults.
+tcfft_status choose(const Desc& d, Choice* ch, bool* tuned, double* tuned_us) {
+  const std::string key = tune_key(d);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *ch = it->second.first;
+      *tuned = true;
+      *tuned_us = it->second.second;
+      return TCFFT_OK;
+    }
+  }
+  *ch = Choice{};
+  *tuned = false;
+  *tuned_us = 0.0;
+  if (!(d.flags & TCFFT_FLAG_TUNE)) return TCFFT_OK;
+  std::vector<Choice> cands = candidates(d);
+  if (cands.size() <= 1) return TCFFT_OK;
+  // tune on at most 2^26 points per buffer (same kernels, fewer workgroups)
+  Desc dt = d;
+  const int64_t npts = d.nx * d.ny;
+  dt.batch = std::max<int64_t>(1, std::min<int64_t>(d.batch, ((int64_t)1 << 26) / npts));
+  size_t bytes = 0;
+  std::vector<PlanSpec> specs;
+  for (const Choice& c : cands) {
+    PlanSpec ps;
+    if (build_spec(dt, c, &ps) != TCFFT_OK) continue;
+    bytes = std::max(bytes, ps.buf_bytes);
+    specs.push_back(ps);
+  }
+  if (specs.empty()) return TCFFT_OK;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipFree(a);
+    return TCFFT_ERR_ALLOC;
+  }
+  (void)hipMemset(a, 0, bytes);
+  double best = 1e30;
+  Choice bestc = specs[0].ch;
+  for (const PlanSpec& ps : specs) {
+    double us = 0;
+    if (time_spec(ps, a, b, &us) == TCFFT_OK && us < best) {
+      best = us;
+      bestc = ps.ch;
+    }
+  }
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (best >= 1e30) return TCFFT_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {bestc, best};
+  }
+  *ch = bestc;
+  *tuned = true;
+  *tuned_us = best;
+  return TCFFT_OK;
+}
+
+tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
+  PlanSpec ps;
+  tcfft_status st = build_spec(d, Choice{}, &ps);  // validates the arguments
+  if (st) return st;
+  int dev = 0;
+  if ((st = check_device(&dev, nullptr))) return st;
+  Choice ch;
+  bool tuned = false;
+  double tuned_us = 0.0;
+  if ((st = choose(d, &ch, &tuned, &tuned_us))) return st;
+  if ((st = build_spec(d, ch, &ps))) return st;
+  ps.tuned = tuned;
+  ps.tuned_us = tuned_us;
+  return create_device_plan(ps, out);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -534,11 +920,12 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
   for (int j = 0; j < njobs; ++j)
     if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]))
       return TCFFT_ERR_INVALID_ARG;
-  for (int j = 0; j < njobs; ++j) {
-    tcfft_status st = exec_impl(plans[j], in[j], out[j], (hipStream_t)stream);
-    if (st) return st;
+  if (njobs == 0) return TCFFT_OK;
+  try {
+    return exec_many_impl(plans, in, out, njobs, (hipStream_t)stream);
+  } catch (...) {
+    return TCFFT_ERR_INTERNAL;
   }
-  return TCFFT_OK;
 }
 
 tcfft_status tcfft_plan_destroy(tcfft_plan plan) {
@@ -575,9 +962,80 @@ int tcfft_plan_dry_run(int rank, const int64_t* dims, int64_t batch, int dir, in
   d.prec = precision;
   d.flags = flags;
   PlanSpec ps;
-  tcfft_status st = build_spec(d, &ps);
+  tcfft_status st = build_spec(d, Choice{}, &ps);
   if (st) return -(int)st;
   return copy_out(describe(ps), buf, len);
+}
+
+int tcfft_tune_candidates(int rank, const int64_t* dims, int64_t batch, int precision, char* buf,
+                          size_t len) {
+  if (!dims || (rank != 1 && rank != 2)) return -(int)TCFFT_ERR_INVALID_ARG;
+  Desc d;
+  d.rank = rank;
+  d.nx = dims[0];
+  d.ny = rank == 2 ? dims[1] : 1;
+  d.batch = batch;
+  d.prec = precision;
+  tcfft_status st = validate(d);
+  if (st) return -(int)st;
+  std::string s = "[";
+  bool first = true;
+  for (const Choice& c : candidates(d)) {
+    PlanSpec ps;
+    if (build_spec(d, c, &ps) != TCFFT_OK) continue;
+    s += first ? "" : ",";
+    first = false;
+    s += describe(ps);
+  }
+  s += "]";
+  return copy_out(s, buf, len);
+}
+
+int tcfft_tune_cache_size(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+tcfft_status tcfft_tune_cache_save(const char* path) {
+  if (!path) return TCFFT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return TCFFT_ERR_INVALID_ARG;
+  std::fprintf(f, "tcfft-tune 1\n");
+  for (const auto& kv : g_tune) {
+    const Choice& c = kv.second.first;
+    std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf, c.f[0],
+                 c.f[1], c.f[2], kv.second.second);
+  }
+  std::fclose(f);
+  return TCFFT_OK;
+}
+
+tcfft_status tcfft_tune_cache_load(const char* path) {
+  if (!path) return TCFFT_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return TCFFT_ERR_INVALID_ARG;
+  char key[160];
+  int ver = 0;
+  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 1) {
+    std::fclose(f);
+    return TCFFT_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  Choice c;
+  double us = 0;
+  while (std::fscanf(f, "%159s %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf, &c.f[0],
+                     &c.f[1], &c.f[2], &us) == 8) {
+    if (c.nf < 0 || c.nf > 3) continue;
+    g_tune[key] = {c, us};
+  }
+  std::fclose(f);
+  return TCFFT_OK;
+}
+
+void tcfft_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
 }
 
 const char* tcfft_status_string(tcfft_status s) {
@@ -593,6 +1051,6 @@ const char* tcfft_status_string(tcfft_status s) {
   return "unknown status";
 }
 
-const char* tcfft_version(void) { return "tcfft-mi355x 0.1"; }
+const char* tcfft_version(void) { return "tcfft-mi355x 0.2"; }
 
 }  // extern "C"

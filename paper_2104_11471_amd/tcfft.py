@@ -21,6 +21,7 @@ PREC_SPLIT_FP16 = 1
 PREC_FP32_RADIX2 = 2
 FLAG_NO_SCALE = 1
 FLAG_NO_GRAPH = 2
+FLAG_TUNE = 4
 _PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_FP16,
          "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2}
 
@@ -31,7 +32,11 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "
 EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", "tcfft_exec_many",
            "tcfft_plan_destroy", "tcfft_plan_scale_log2", "tcfft_plan_buffer_bytes",
            "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
-           "tcfft_plan_dry_run", "tcfft_status_string", "tcfft_version"]
+           "tcfft_plan_dry_run", "tcfft_status_string", "tcfft_version", "tcfft_tune_candidates",
+           "tcfft_tune_cache_size", "tcfft_tune_cache_save", "tcfft_tune_cache_load",
+           "tcfft_tune_cache_clear", "tcfft_server_create", "tcfft_server_prepare",
+           "tcfft_server_submit", "tcfft_server_poll", "tcfft_server_wait_idle",
+           "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns"]
 
 
 class TcfftError(RuntimeError):
@@ -68,6 +73,17 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_status_string.restype = ctypes.c_char_p
     lib.tcfft_version.argtypes = []
     lib.tcfft_version.restype = ctypes.c_char_p
+    lib.tcfft_tune_candidates.argtypes = [ctypes.c_int, P(i64), i64, ctypes.c_int, ctypes.c_char_p,
+                                          ctypes.c_size_t]
+    lib.tcfft_tune_candidates.restype = ctypes.c_int
+    lib.tcfft_tune_cache_size.argtypes = []
+    lib.tcfft_tune_cache_size.restype = ctypes.c_int
+    lib.tcfft_tune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.tcfft_tune_cache_save.restype = ctypes.c_int
+    lib.tcfft_tune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.tcfft_tune_cache_load.restype = ctypes.c_int
+    lib.tcfft_tune_cache_clear.argtypes = []
+    lib.tcfft_tune_cache_clear.restype = None
     for name in ("tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec",
                  "tcfft_exec_many", "tcfft_plan_destroy", "tcfft_plan_scale_log2",
                  "tcfft_plan_num_launches", "tcfft_plan_describe", "tcfft_plan_dry_run"):
@@ -92,6 +108,37 @@ def dry_run(dims, batch: int, direction: int = FORWARD, precision="fp16", flags:
     if n < 0:
         raise TcfftError(-n, "tcfft_plan_dry_run")
     return json.loads(buf.value.decode())
+
+
+def tune_candidates(dims, batch: int, precision="fp16") -> list:
+    """The planner candidates the autotuner times (no device)."""
+    dims = tuple(int(d) for d in dims)
+    arr = (ctypes.c_int64 * len(dims))(*dims)
+    buf = ctypes.create_string_buffer(1 << 20)
+    n = lib.tcfft_tune_candidates(len(dims), arr, int(batch), _prec(precision), buf, len(buf))
+    if n < 0:
+        raise TcfftError(-n, "tcfft_tune_candidates")
+    return json.loads(buf.value.decode())
+
+
+def tune_cache_save(path: str) -> None:
+    st = lib.tcfft_tune_cache_save(path.encode())
+    if st != 0:
+        raise TcfftError(st, "tcfft_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> None:
+    st = lib.tcfft_tune_cache_load(path.encode())
+    if st != 0:
+        raise TcfftError(st, "tcfft_tune_cache_load")
+
+
+def tune_cache_size() -> int:
+    return int(lib.tcfft_tune_cache_size())
+
+
+def tune_cache_clear() -> None:
+    lib.tcfft_tune_cache_clear()
 
 
 class Plan:

@@ -136,3 +136,34 @@ def test_null_arguments(tc):
     h = ctypes.c_void_p()
     assert lib.tcfft_plan_create(ctypes.byref(h), 3, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
     assert lib.tcfft_plan_create(None, 1, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
+
+
+def test_tune_candidates_are_valid_plans(tc):
+    for dims in [(4096,), (16384,), (65536,), (1 << 20,), (1 << 24,), (256, 256), (1024, 1024)]:
+        cands = tc.tune_candidates(dims, 8)
+        assert len(cands) >= 1
+        n = dims[0] * (dims[1] if len(dims) == 2 else 1)
+        for d in cands:
+            prod = 1
+            for p in d["passes"]:
+                prod *= p["L"]
+                assert p["lds"] <= 160 * 1024
+            assert prod == n
+
+
+def test_tune_cache_file_errors(tc, tmp_path):
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a cache\n")
+    with pytest.raises(tc.TcfftError):
+        tc.tune_cache_load(str(bad))
+    with pytest.raises(tc.TcfftError):
+        tc.tune_cache_load(str(tmp_path / "missing.txt"))
+    tc.tune_cache_clear()
+    assert tc.tune_cache_size() == 0
+    good = tmp_path / "good.txt"
+    good.write_text("tcfft-tune 1\nr1_4096x1_b8_p0 512 64 0 0 0 0 123.000\n")
+    tc.tune_cache_load(str(good))
+    assert tc.tune_cache_size() == 1
+    tc.tune_cache_save(str(tmp_path / "out.txt"))
+    assert "r1_4096x1_b8_p0 512 64" in (tmp_path / "out.txt").read_text()
+    tc.tune_cache_clear()
