@@ -122,6 +122,30 @@ def cpu_baseline(xs, target_s: float):
                       + f"), {total_t:.1f} s"}
 
 
+def serving_leg(seconds: float) -> dict:
+    """Poisson stream (20k req/s) of the mixed request population through the
+    continuous-batching scheduler: p50/p99 latency and throughput.  Payloads
+    are pre-staged in device memory (at these rates they would exceed PCIe)."""
+    from paper_2104_11471_amd import inputs, serve
+    reqs = inputs.serving_stream(rate_hz=20000.0, duration_s=seconds, seed=0)
+    pool = serve.PayloadPool(reqs, slots=12)
+    srv = serve.Server(nslots=4, mem_budget_bytes=24 << 30, max_batch_jobs=512)
+    srv.prepare({(r.rank, tuple(r.dims), -1, "split" if r.split else "fp16") for r in reqs})
+    # warm the kernels once with the first few requests
+    serve.run_stream(srv, reqs[:64], pool)
+    t0 = serve.now_ns()
+    recs, _ = serve.run_stream(srv, reqs, pool)
+    wall = (serve.now_ns() - t0) / 1e9
+    out = serve.summarize(recs, wall)
+    st = srv.stats()
+    out.update({"offered_req_per_s": 20000.0, "seconds": seconds, "slots": 4,
+                "batches": st["batches"], "max_batch_jobs": st["max_batch_jobs"],
+                "max_inflight_bytes": st["max_inflight_bytes"],
+                "payload_pool_bytes": pool.nbytes()})
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated subset of the sizes (profiling)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="length of the Poisson serving stream (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -225,6 +251,11 @@ def main():
         log(f"fp32 radix-2 comparator: {comparator}")
         del x32, y32, p32
 
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serving_leg(args.serve_seconds)
+        log(f"serving: {serving}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(xs, args.cpu_seconds)
@@ -243,6 +274,7 @@ def main():
         "per_size": {str(k): v for k, v in per.items()},
         "roofline": roofline,
         "comparator_fp32_radix2": comparator,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -197,6 +197,9 @@ typedef struct {
   int max_batch_jobs;      /* >= 1 requests per batch */
   size_t mem_budget_bytes; /* > 0: payload + workspace of all requests in flight */
   size_t arena_bytes;      /* workspace arena per slot; 0 = mem_budget_bytes / nslots */
+  int use_graphs;          /* nonzero: each slot captures its grouped launches as a HIP graph
+                              once per kernel-variant sequence and replays it (descriptor
+                              tables are rewritten in device memory per batch) */
 } tcfft_server_config;
 
 typedef struct {

@@ -50,9 +50,17 @@ struct KernelKey {
   int tstore;  // column kernel: transposed store (row of L contiguous outputs)
 };
 
+// Header of one grouped launch, in device memory: job j of the group owns
+// workgroups [prefix[j], prefix[j+1]) and is described by jobs[j].
+struct GroupHdr {
+  const KParams* jobs;
+  const int64_t* prefix;  // njobs + 1 entries
+  int64_t njobs;
+  int64_t reserved;
+};
+
 typedef void (*KernelFn)(KParams);
-// Grouped launch: (descriptor table, prefix of workgroups per job, job count).
-typedef void (*MultiFn)(const KParams*, const int64_t*, int);
+typedef void (*MultiFn)(const GroupHdr*);
 
 struct KernelFns {
   KernelFn single = nullptr;

@@ -176,7 +176,11 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
   for (int k = 1; k < R0; ++k)
 #pragma unroll
     for (int t = 1; t < 4; ++t) bt[k][t] = kp.tw[k * t];
-  for (int cq = threadIdx.x; cq < G::NCQ0; cq += G::NT) {
+  constexpr int ITER = (G::NCQ0 + G::NT - 1) / G::NT;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int cq = threadIdx.x + it * G::NT;
+    if (G::NCQ0 % G::NT != 0 && cq >= G::NCQ0) break;
     const int col0 = 4 * cq;
     const int tau = col0 / P0;
     const int lo0 = col0 % P0;
@@ -430,7 +434,11 @@ template <class G, bool SPLIT>
 __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, const ColCtx& cx) {
   constexpr int L = G::L, R0 = G::R0, C = G::C, P0 = G::P0;
   uint32_t* ldsl = lds + G::PTS;
-  for (int cq = threadIdx.x; cq < G::NCQ0; cq += G::NT) {
+  constexpr int ITER = (G::NCQ0 + G::NT - 1) / G::NT;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int cq = threadIdx.x + it * G::NT;
+    if (G::NCQ0 % G::NT != 0 && cq >= G::NCQ0) break;
     const int col0 = 4 * cq;
     const int c = col0 % C;
     const int lo = col0 / C;  // in [0, P0)
@@ -595,22 +603,28 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
     __syncthreads();
     // transposed store: column c of the tile becomes a row of L natural-order
     // outputs; output k sits at position posrev_hi(k mod L/16) * 16 + k / (L/16).
-    // Each task reads 4 adjacent columns of one output (16 bytes of LDS) and
-    // writes them to 4 rows; adjacent lanes take adjacent k, so every store
-    // instruction writes 256 contiguous bytes of a row.
-    for (int task = threadIdx.x; task < (C / 4) * L; task += G::NT) {
-      const int c4 = 4 * (task / L);
-      const int k = task % L;
-      const int j = posrev_hi<R0, S>(k % (L / 16)) * 16 + k / (L / 16);
-      const u4 h = lds_ld4(lds, j * C + c4);
-      u4 l = {0, 0, 0, 0};
-      if constexpr (SPLIT) l = lds_ld4(ldsl, j * C + c4);
+    // Each task gathers 4 consecutive outputs of one column from LDS and
+    // writes them as one 16-byte store; adjacent lanes take adjacent k, so a
+    // wave writes 1 KB of a row per instruction.
+    constexpr int TASKS = C * (L / 4);
+    constexpr int ITER = (TASKS + G::NT - 1) / G::NT;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t a = cx.out_base + (int64_t)(c4 + t) * L + k;
-        kp.out[a] = h[t];
-        if constexpr (SPLIT) kp.out[kp.out_plane + a] = l[t];
+    for (int it = 0; it < ITER; ++it) {
+      const int task = threadIdx.x + it * G::NT;
+      if (TASKS % G::NT != 0 && task >= TASKS) break;
+      const int c = task / (L / 4);
+      const int k0 = 4 * (task % (L / 4));
+      u4 h, l = {0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + i;
+        const int j = posrev_hi<R0, S>(k % (L / 16)) * 16 + k / (L / 16);
+        h[i] = lds_ld1(lds, j * C + c);
+        if constexpr (SPLIT) l[i] = lds_ld1(ldsl, j * C + c);
       }
+      const int64_t a = cx.out_base + (int64_t)c * L + k0;
+      gst4(kp.out + a, h);
+      if constexpr (SPLIT) gst4(kp.out + kp.out_plane + a, l);
     }
   }
 }
@@ -660,9 +674,11 @@ __global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
 // ===========================================================================
 // Grouped mixed-size launch: one launch runs the same pass kernel for many
 // jobs (different sizes of batch, buffers, tables).  Job j owns workgroup
-// indices [prefix[j], prefix[j+1]); the descriptor table and the prefix array
-// live in device memory, so a captured launch can be replayed with new jobs.
-// The grid is persistent: each workgroup strides over the job tiles.
+// indices [prefix[j], prefix[j+1]).  The launch's only argument is a group
+// header in device memory that points at the descriptor table and the prefix
+// array, so a captured launch can be replayed for a new set of jobs by
+// rewriting device memory.  The grid is persistent: each workgroup strides
+// over the job tiles.
 // ===========================================================================
 __device__ __forceinline__ int find_job(const int64_t* __restrict__ prefix, int njobs, int64_t w) {
   int lo = 0, hi = njobs - 1;  // largest j with prefix[j] <= w
@@ -675,11 +691,12 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ prefix, int 
 }
 
 template <int L, int R0, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT) void row_kernel_multi(const KParams* __restrict__ jobs,
-                                                       const int64_t* __restrict__ prefix,
-                                                       int njobs) {
+__global__ __launch_bounds__(NT) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
-  const int64_t total = prefix[njobs];
+  const KParams* __restrict__ jobs = hdr->jobs;
+  const int64_t* __restrict__ prefix = hdr->prefix;
+  const int njobs = (int)hdr->njobs;
+  const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
     const KParams kp = jobs[j];
@@ -689,11 +706,12 @@ __global__ __launch_bounds__(NT) void row_kernel_multi(const KParams* __restrict
 }
 
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
-__global__ __launch_bounds__(NT) void col_kernel_multi(const KParams* __restrict__ jobs,
-                                                       const int64_t* __restrict__ prefix,
-                                                       int njobs) {
+__global__ __launch_bounds__(NT) void col_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
-  const int64_t total = prefix[njobs];
+  const KParams* __restrict__ jobs = hdr->jobs;
+  const int64_t* __restrict__ prefix = hdr->prefix;
+  const int njobs = (int)hdr->njobs;
+  const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
     const KParams kp = jobs[j];

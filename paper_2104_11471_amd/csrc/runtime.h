@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
+
 #include "../../include/tcfft.h"
 
 namespace tcfft {
@@ -20,10 +23,25 @@ struct Job {
   void* ws;
 };
 
+// Instantiated graphs of grouped launches, keyed by the sequence of kernel
+// variants of a batch (owned by one stream / descriptor arena).
+struct GraphCache {
+  std::map<std::string, void*> execs;  // hipGraphExec_t
+  ~GraphCache();
+};
+
 }  // namespace tcfft
 
 // Grouped mixed-size launch of `njobs` jobs on stream `s` (see tcfft_exec_many).
-tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s);
+// With desc_arena (device, arena_cap bytes, owned by this stream) the
+// descriptor tables go there instead of a stream-ordered allocation; with
+// graphs as well, the launch sequence is captured once per variant sequence
+// and replayed as a HIP graph.
+tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s,
+                                      void* desc_arena, size_t arena_cap,
+                                      tcfft::GraphCache* graphs);
+// Descriptor arena bytes that always suffice for a batch of max_jobs jobs.
+size_t tcfft_internal_desc_bytes(int max_jobs);
 size_t tcfft_internal_plan_ws_bytes(const tcfft_plan_s* p, int64_t batch);
 int64_t tcfft_internal_plan_batch(const tcfft_plan_s* p);
 int64_t tcfft_internal_plan_points(const tcfft_plan_s* p);

@@ -54,6 +54,9 @@ struct Slot {
   hipEvent_t ev = nullptr;
   void* arena = nullptr;
   size_t arena_cap = 0;
+  void* desc = nullptr;  // descriptor arena (fixed address: graphs replay against it)
+  size_t desc_cap = 0;
+  tcfft::GraphCache* graphs = nullptr;
   bool busy = false;
   std::vector<Req> reqs;
   size_t bytes = 0;
@@ -183,7 +186,8 @@ bool dispatch(tcfft_server_s* s, Slot& sl) {
   sl.bytes = bytes;
   sl.t_start = now_ns();
   sl.batch_id = s->next_batch++;
-  tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), sl.stream);
+  tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), sl.stream, sl.desc,
+                                             sl.desc_cap, s->cfg.use_graphs ? sl.graphs : nullptr);
   if (st == TCFFT_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = TCFFT_ERR_LAUNCH;
   if (st != TCFFT_OK) {
     (void)hipGetLastError();
@@ -258,12 +262,16 @@ tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* c
   s->slots.resize(cfg->nslots);
   // each slot's arena may hold the workspace of a full budget's worth of jobs
   const size_t arena = align_up(cfg->arena_bytes ? cfg->arena_bytes : cfg->mem_budget_bytes / cfg->nslots);
+  const size_t desc = tcfft_internal_desc_bytes(cfg->max_batch_jobs);
   for (Slot& sl : s->slots) {
+    sl.graphs = new tcfft::GraphCache();
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&sl.arena, arena) != hipSuccess) {
+        hipMalloc(&sl.arena, arena) != hipSuccess || hipMalloc(&sl.desc, desc) != hipSuccess) {
       (void)hipGetLastError();
       for (Slot& t : s->slots) {
+        delete t.graphs;
+        if (t.desc) (void)hipFree(t.desc);
         if (t.arena) (void)hipFree(t.arena);
         if (t.ev) (void)hipEventDestroy(t.ev);
         if (t.stream) (void)hipStreamDestroy(t.stream);
@@ -272,6 +280,7 @@ tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* c
       return TCFFT_ERR_ALLOC;
     }
     sl.arena_cap = arena;
+    sl.desc_cap = desc;
   }
   s->worker = std::thread(run, s);
   *out = s;
@@ -353,6 +362,8 @@ tcfft_status tcfft_server_destroy(tcfft_server s) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
   }
   for (Slot& sl : s->slots) {
+    delete sl.graphs;
+    if (sl.desc) (void)hipFree(sl.desc);
     if (sl.arena) (void)hipFree(sl.arena);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);

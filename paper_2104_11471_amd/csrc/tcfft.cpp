@@ -630,7 +630,18 @@ struct Group {
 
 }  // namespace
 
-tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s) {
+size_t tcfft_internal_desc_bytes(int max_jobs) {
+  // <= 3 pass levels: per level at most one group per job
+  return (size_t)3 * (size_t)max_jobs * (sizeof(GroupHdr) + sizeof(KParams) + 2 * sizeof(int64_t)) + 4096;
+}
+
+tcfft::GraphCache::~GraphCache() {
+  for (auto& kv : execs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+}
+
+tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s,
+                                      void* desc_arena, size_t arena_cap,
+                                      tcfft::GraphCache* graphs) {
   int levels = 0;
   for (int j = 0; j < njobs; ++j) {
     tcfft_plan_s* p = jobs[j].plan;
@@ -641,13 +652,16 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     }
     levels = std::max(levels, (int)p->dp.size());
   }
+  // every (pass level, variant) group of the batch, in launch order
+  std::vector<Group> groups;
+  std::vector<KernelKey> keys;
   for (int lv = 0; lv < levels; ++lv) {
-    std::map<KernelKey, Group, KeyLess> groups;
+    std::map<KernelKey, Group, KeyLess> lg;
     for (int j = 0; j < njobs; ++j) {
       tcfft_plan_s* p = jobs[j].plan;
       if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || lv >= (int)p->dp.size()) continue;
       const DevPass& dpp = p->dp[lv];
-      Group& g = groups[dpp.spec.key];
+      Group& g = lg[dpp.spec.key];
       g.fn = dpp.fn;
       g.nt = dpp.spec.key.NT;
       g.lds = dpp.spec.lds;
@@ -656,33 +670,91 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
       g.jobs.push_back(make_kparams(p, dpp, jobs[j].in, jobs[j].out, jobs[j].batch, jobs[j].ws, &grid));
       g.prefix.push_back(g.prefix.back() + grid);
     }
-    for (auto& kv : groups) {
-      Group& g = kv.second;
-      const int n = (int)g.jobs.size();
-      const size_t jb = (size_t)n * sizeof(KParams), pb = (size_t)(n + 1) * sizeof(int64_t);
-      void* dmem = nullptr;
-      if (hipMallocAsync(&dmem, jb + pb, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return TCFFT_ERR_ALLOC;
-      }
-      std::vector<uint8_t> host(jb + pb);
-      std::memcpy(host.data(), g.jobs.data(), jb);
-      std::memcpy(host.data() + jb, g.prefix.data(), pb);
-      tcfft_status ust = upload(dmem, host.data(), jb + pb, s);
-      if (ust) return ust;
-      const KParams* djobs = (const KParams*)dmem;
-      const int64_t* dprefix = (const int64_t*)((uint8_t*)dmem + jb);
-      const int64_t total = g.prefix.back();
-      const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(total, g.persist));
-      void* args[] = {&djobs, &dprefix, (void*)&n};
+    for (auto& kv : lg) {
+      keys.push_back(kv.first);
+      groups.push_back(std::move(kv.second));
+    }
+  }
+  if (groups.empty()) return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
+  // one upload for the whole batch: the group headers, then per group its
+  // KParams table and prefix array (all 8-byte aligned)
+  const size_t G = groups.size();
+  std::vector<size_t> off(G);
+  size_t total_bytes = G * sizeof(GroupHdr);
+  for (size_t i = 0; i < G; ++i) {
+    off[i] = total_bytes;
+    total_bytes += groups[i].jobs.size() * sizeof(KParams) + groups[i].prefix.size() * sizeof(int64_t);
+  }
+  uint8_t* dmem = (uint8_t*)desc_arena;
+  if (dmem && total_bytes > arena_cap) return TCFFT_ERR_ALLOC;
+  if (!dmem) {
+    void* m = nullptr;
+    if (hipMallocAsync(&m, total_bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_ALLOC;
+    }
+    dmem = (uint8_t*)m;
+  }
+  std::vector<uint8_t> host(total_bytes);
+  for (size_t i = 0; i < G; ++i) {
+    const size_t jb = groups[i].jobs.size() * sizeof(KParams);
+    GroupHdr h{};
+    h.jobs = (const KParams*)(dmem + off[i]);
+    h.prefix = (const int64_t*)(dmem + off[i] + jb);
+    h.njobs = (int64_t)groups[i].jobs.size();
+    std::memcpy(host.data() + i * sizeof(GroupHdr), &h, sizeof h);
+    std::memcpy(host.data() + off[i], groups[i].jobs.data(), jb);
+    std::memcpy(host.data() + off[i] + jb, groups[i].prefix.data(),
+                groups[i].prefix.size() * sizeof(int64_t));
+  }
+  tcfft_status st = upload(dmem, host.data(), total_bytes, s);
+  if (st) return st;
+  auto launch_all = [&](bool full_grid) -> tcfft_status {
+    for (size_t i = 0; i < G; ++i) {
+      const Group& g = groups[i];
+      const GroupHdr* hdr = (const GroupHdr*)(dmem + i * sizeof(GroupHdr));
+      const int64_t want = full_grid ? g.persist : std::min<int64_t>(g.prefix.back(), g.persist);
+      const unsigned grid = (unsigned)std::max<int64_t>(1, want);
+      void* args[] = {&hdr};
       if (hipLaunchKernel((const void*)g.fn.multi, dim3(grid), dim3(g.nt), args, g.lds, s) !=
           hipSuccess) {
         (void)hipGetLastError();
         return TCFFT_ERR_LAUNCH;
       }
-      (void)hipFreeAsync(dmem, s);  // stream-ordered: after the launch has run
     }
+    return TCFFT_OK;
+  };
+  if (graphs && desc_arena) {
+    // the captured launches depend only on the variant sequence and on the
+    // fixed header addresses, so one graph serves every batch of that shape
+    const std::string sig((const char*)keys.data(), keys.size() * sizeof(KernelKey));
+    auto it = graphs->execs.find(sig);
+    if (it == graphs->execs.end()) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
+      tcfft_status lst = launch_all(true);
+      const hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (lst || ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        return lst ? lst : TCFFT_ERR_LAUNCH;
+      }
+      (void)hipGraphDestroy(graph);
+      it = graphs->execs.emplace(sig, (void*)exec).first;
+    }
+    if (hipGraphLaunch((hipGraphExec_t)it->second, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_LAUNCH;
+    }
+  } else {
+    st = launch_all(false);
+    if (st) return st;
   }
+  if (!desc_arena) (void)hipFreeAsync(dmem, s);  // stream-ordered: after the launches
   return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
 }
 
@@ -703,7 +775,7 @@ tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void
   std::vector<Job> jobs(njobs);
   for (int j = 0; j < njobs; ++j)
     jobs[j] = Job{plans[j], in[j], const_cast<void*>(out[j]), plans[j]->spec.d.batch, plans[j]->ws};
-  return tcfft_internal_exec_jobs(jobs.data(), njobs, s);
+  return tcfft_internal_exec_jobs(jobs.data(), njobs, s, nullptr, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------

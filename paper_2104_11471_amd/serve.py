@@ -20,7 +20,8 @@ lib = _tc.lib
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("nslots", ctypes.c_int), ("max_batch_jobs", ctypes.c_int),
-                ("mem_budget_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t)]
+                ("mem_budget_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t),
+                ("use_graphs", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -76,8 +77,8 @@ def _request(rank, dims, batch, direction, precision, in_ptr=0, out_ptr=0, tag=0
 
 class Server:
     def __init__(self, nslots: int = 4, mem_budget_bytes: int = 16 << 30, max_batch_jobs: int = 256,
-                 arena_bytes: int = 0):
-        cfg = ServerConfig(nslots, max_batch_jobs, mem_budget_bytes, arena_bytes)
+                 arena_bytes: int = 0, use_graphs: bool = True):
+        cfg = ServerConfig(nslots, max_batch_jobs, mem_budget_bytes, arena_bytes, int(use_graphs))
         h = ctypes.c_void_p()
         st = lib.tcfft_server_create(ctypes.byref(h), ctypes.byref(cfg))
         if st != 0:
