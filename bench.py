@@ -60,7 +60,8 @@ def measured_traffic(kernel_name: str):
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
-        src = open(os.path.join(ROOT, "paper_2104_11471_amd", "csrc", "kernels.hip"), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_2104_11471_amd", "csrc", f), "rb").read()
+                       for f in ("common.h", "pass_kernels.h"))
     except OSError:
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernels_sha256_16"):
@@ -122,6 +123,62 @@ def cpu_baseline(xs, target_s: float):
                       + f"), {total_t:.1f} s"}
 
 
+def other_workloads(stream) -> dict:
+    """Timing + sampled accuracy of the other workloads: the N=256 x 64 latency
+    case, long 1D (2^20 x 16, 2^22 x 4, 2^24 x 1) and batched 2D (256^2 x 1024,
+    512^2 x 256, 1024^2 x 64), FP16 and split.  Not part of `value`."""
+    import torch
+    import oracle
+    from paper_2104_11471_amd import inputs, tcfft
+    out = {}
+    # latency of the small case (unnormalised, as specified)
+    x = torch.from_numpy(inputs.uniform((64, 256), 0)).cuda()
+    p = tcfft.Plan((256,), 64, flags=tcfft.FLAG_NO_SCALE)
+    y = torch.empty_like(x)
+    for _ in range(20):
+        p(x, y, stream=stream)
+    dt = time_launches(lambda: p(x, y, stream=stream), 200, stream)
+    out["1d_256x64"] = {"us": round(dt * 1e6, 2)}
+    cases = [("1d", (1 << 20,), 16), ("1d", (1 << 22,), 4), ("1d", (1 << 24,), 1),
+             ("2d", (256, 256), 1024), ("2d", (512, 512), 256), ("2d", (1024, 1024), 64)]
+    for kind, dims, batch in cases:
+        for prec in ("fp16", "split"):
+            split = prec == "split"
+            if kind == "1d":
+                xh, _, _ = inputs.long_1d(dims[0], batch, seed=0, as_split=split)
+            else:
+                xh = inputs.smooth_2d(dims[0], dims[1], batch, seed=0, as_split=split)
+            host = np.stack(xh) if split else xh
+            xd = torch.from_numpy(host).cuda()
+            yd = torch.empty_like(xd)
+            p = tcfft.Plan(dims, batch, precision=prec)
+            p(xd, yd, stream=stream)
+            dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
+            npts = int(np.prod(dims)) * batch
+            n = int(np.prod(dims))
+            row = 0
+            z = (yd[:, row] if split else yd[row]).cpu().numpy().astype(np.float64)
+            if split:
+                z = (z[0, ..., 0] + 2.0 ** -11 * z[1, ..., 0]) + 1j * (z[0, ..., 1] + 2.0 ** -11 * z[1, ..., 1])
+                zin = oracle.from_split(xh[0][row], xh[1][row])
+            else:
+                z = z[..., 0] + 1j * z[..., 1]
+                zin = oracle.from_half(xh[row])
+            ref = oracle.fft(zin) if kind == "1d" else oracle.fft2(zin)
+            err = float(oracle.rel_l2(z * 2.0 ** p.scale_log2, ref, axis=None))
+            bpp = 16 if split else 8
+            key = f"{kind}_{'x'.join(map(str, dims))}x{batch}_{prec}"
+            out[key] = {"us": round(dt * 1e6, 1),
+                        "gflops": round(5.0 * n * math.log2(n) * batch / dt / 1e9, 1),
+                        "gbs_alg": round(bpp * npts / dt / 1e9, 1),
+                        "hbm_frac_alg": round(bpp * npts / dt / 1e9 / HBM_PEAK_GBS, 4),
+                        "passes": p.num_launches, "rel_l2_row0": err}
+            log(f"{key}: {out[key]}")
+            del xd, yd, p
+            torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(seconds: float) -> dict:
     """Poisson stream (20k req/s) of the mixed request population through the
     continuous-batching scheduler: p50/p99 latency and throughput.  Payloads
@@ -155,6 +212,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated subset of the sizes (profiling)")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of the Poisson serving stream (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -251,6 +309,10 @@ def main():
         log(f"fp32 radix-2 comparator: {comparator}")
         del x32, y32, p32
 
+    others = None
+    if not args.no_others:
+        others = other_workloads(stream)
+
     serving = None
     if args.serve_seconds > 0:
         serving = serving_leg(args.serve_seconds)
@@ -275,6 +337,7 @@ def main():
         "roofline": roofline,
         "comparator_fp32_radix2": comparator,
         "serving": serving,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -79,6 +79,8 @@ struct Choice {
   int cmax = 64;     // widest column block a column pass may use
   int nf = 0;        // 0: default factorisation of long 1D lengths; else pass lengths f[]
   int f[3] = {0, 0, 0};
+  int chunk = 0;     // multi-pass plans: transforms per chunk (0 = whole batch); all passes
+                     // of a chunk run before the next chunk, reusing one workspace region
 };
 
 struct PlanSpec {
@@ -269,6 +271,8 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     if (!st) st = add_col_pass(ps, (int)nx, ny, B, nx * ny, nx * ny, ny, ny, 0, false, 0, 1, 1, 1);
   }
   if (st) return st;
+  if (d.prec == TCFFT_PREC_FP16 && ch.chunk > 0 && ch.chunk < B && ps.ws_bytes > 0)
+    ps.ws_bytes = (size_t)((double)ps.ws_bytes * (double)ch.chunk / (double)B);
   if (d.flags & TCFFT_FLAG_NO_SCALE)
     for (auto& p : ps.passes) p.scale = 0;
   ps.scale = 0;
@@ -284,13 +288,13 @@ std::string describe(const PlanSpec& ps) {
   std::snprintf(b, sizeof b,
                 "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,"
-                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d]},\"tuned\":%s,"
+                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d},\"tuned\":%s,"
                 "\"tuned_us\":%.2f,\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
                 ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
                 precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes, ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
-                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.tuned ? "true" : "false", ps.tuned_us);
+                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.tuned ? "true" : "false", ps.tuned_us);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
@@ -547,15 +551,32 @@ tcfft_status exec_r2(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) 
 }
 
 tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
-  if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return exec_r2(p, in, out, s);
-  for (const DevPass& dpp : p->dp) {
-    int64_t grid = 0;
-    KParams kp = make_kparams(p, dpp, in, out, p->spec.d.batch, p->ws, &grid);
-    void* args[] = {&kp};
-    if (hipLaunchKernel((const void*)dpp.fn.single, dim3((unsigned)grid),
-                        dim3(dpp.spec.key.NT), args, dpp.spec.lds, s) != hipSuccess) {
-      (void)hipGetLastError();
-      return TCFFT_ERR_LAUNCH;
+  const PlanSpec& ps = p->spec;
+  if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) return exec_r2(p, in, out, s);
+  const int64_t B = ps.d.batch;
+  // chunked execution of multi-pass plans: every pass of a chunk before the
+  // next chunk, the workspace region reused, so the intermediate of a chunk
+  // can stay in the memory-side cache.  Split planes move with the chunk.
+  const bool split = ps.d.prec == TCFFT_PREC_SPLIT_FP16;
+  const int64_t chunk =
+      (!split && ps.ch.chunk > 0 && ps.ch.chunk < B && p->dp.size() > 1) ? ps.ch.chunk : B;
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    const void* cin = in;
+    void* cout = out;
+    if (chunk != B) {
+      cin = (const uint32_t*)in + b0 * ps.npts;
+      cout = (uint32_t*)out + b0 * ps.npts;
+    }
+    for (const DevPass& dpp : p->dp) {
+      int64_t grid = 0;
+      KParams kp = make_kparams(p, dpp, cin, cout, nb, p->ws, &grid);
+      void* args[] = {&kp};
+      if (hipLaunchKernel((const void*)dpp.fn.single, dim3((unsigned)grid),
+                          dim3(dpp.spec.key.NT), args, dpp.spec.lds, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
     }
   }
   return TCFFT_OK;
@@ -772,10 +793,21 @@ namespace {
 
 tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void* const* out,
                             int njobs, hipStream_t s) {
-  std::vector<Job> jobs(njobs);
-  for (int j = 0; j < njobs; ++j)
-    jobs[j] = Job{plans[j], in[j], const_cast<void*>(out[j]), plans[j]->spec.d.batch, plans[j]->ws};
-  return tcfft_internal_exec_jobs(jobs.data(), njobs, s, nullptr, 0, nullptr);
+  std::vector<Job> jobs;
+  jobs.reserve(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const PlanSpec& ps = plans[j]->spec;
+    if (ps.d.prec == TCFFT_PREC_FP16 && ps.ch.chunk > 0 && ps.ch.chunk < ps.d.batch &&
+        plans[j]->dp.size() > 1) {
+      // a chunked plan's workspace holds one chunk: it runs on its own
+      tcfft_status st = exec_impl(plans[j], in[j], out[j], s);
+      if (st) return st;
+      continue;
+    }
+    jobs.push_back(Job{plans[j], in[j], const_cast<void*>(out[j]), ps.d.batch, plans[j]->ws});
+  }
+  if (jobs.empty()) return TCFFT_OK;
+  return tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), s, nullptr, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -793,7 +825,28 @@ std::string tune_key(const Desc& d) {
   return b;
 }
 
+std::vector<Choice> candidates_base(const Desc& d);
+
+// Adds chunked variants (64 MB and 128 MB of FP16 data per chunk) of every
+// multi-pass FP16 candidate.
 std::vector<Choice> candidates(const Desc& d) {
+  std::vector<Choice> base = candidates_base(d);
+  const bool multipass = d.rank == 2 || d.nx > kMaxRowL;
+  if (!multipass || d.prec != TCFFT_PREC_FP16) return base;
+  std::vector<Choice> out = base;
+  const int64_t per = d.nx * d.ny * 4;  // bytes of one FP16 transform
+  for (int64_t mb : {64, 128}) {
+    const int64_t c = std::max<int64_t>(1, (mb << 20) / per);
+    if (c >= d.batch) continue;
+    for (Choice ch : base) {
+      ch.chunk = (int)c;
+      out.push_back(ch);
+    }
+  }
+  return out;
+}
+
+std::vector<Choice> candidates_base(const Desc& d) {
   std::vector<Choice> out;
   if (d.prec == TCFFT_PREC_FP32_RADIX2) return out;
   const bool longp = d.rank == 1 && d.nx > kMaxRowL;
@@ -1073,11 +1126,11 @@ tcfft_status tcfft_tune_cache_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return TCFFT_ERR_INVALID_ARG;
-  std::fprintf(f, "tcfft-tune 1\n");
+  std::fprintf(f, "tcfft-tune 2\n");
   for (const auto& kv : g_tune) {
     const Choice& c = kv.second.first;
-    std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf, c.f[0],
-                 c.f[1], c.f[2], kv.second.second);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf,
+                 c.f[0], c.f[1], c.f[2], c.chunk, kv.second.second);
   }
   std::fclose(f);
   return TCFFT_OK;
@@ -1089,15 +1142,15 @@ tcfft_status tcfft_tune_cache_load(const char* path) {
   if (!f) return TCFFT_ERR_INVALID_ARG;
   char key[160];
   int ver = 0;
-  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 1) {
+  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 2) {
     std::fclose(f);
     return TCFFT_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   Choice c;
   double us = 0;
-  while (std::fscanf(f, "%159s %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf, &c.f[0],
-                     &c.f[1], &c.f[2], &us) == 8) {
+  while (std::fscanf(f, "%159s %d %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf,
+                     &c.f[0], &c.f[1], &c.f[2], &c.chunk, &us) == 9) {
     if (c.nf < 0 || c.nf > 3) continue;
     g_tune[key] = {c, us};
   }

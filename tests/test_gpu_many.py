@@ -94,3 +94,26 @@ def test_autotuned_plan(dims, batch, tmp_path):
     tcfft.tune_cache_load(path)
     q = tcfft.Plan(dims, batch)   # no TUNE flag: the cached choice is reused
     assert q.describe()["choice"] == d["choice"] and q.describe()["tuned"]
+
+
+@pytest.mark.parametrize("dims,batch,chunk", [((65536,), 64, 16), ((1 << 20,), 8, 3),
+                                              ((256, 256), 32, 5)])
+def test_chunked_execution_is_bitwise_equal(dims, batch, chunk, tmp_path):
+    """A multi-pass plan run chunk by chunk (workspace reused per chunk, the
+    MALL-residency knob) gives the same bits as the whole-batch run."""
+    import torch
+    from paper_2104_11471_amd import tcfft
+    tcfft.tune_cache_clear()
+    x = torch.from_numpy(inputs.uniform((batch, *dims), 21)).cuda()
+    whole = tcfft.Plan(dims, batch)(x)
+    key = f"r{len(dims)}_{dims[0]}x{dims[1] if len(dims) == 2 else 1}_b{int(np.log2(batch))}_p0"
+    path = tmp_path / "wisdom.txt"
+    path.write_text(f"tcfft-tune 2\n{key} 256 64 0 0 0 0 {chunk} 1.0\n")
+    tcfft.tune_cache_load(str(path))
+    p = tcfft.Plan(dims, batch)
+    assert p.describe()["choice"]["chunk"] == chunk
+    assert p.workspace_bytes < tcfft.Plan(dims, 1).workspace_bytes * batch
+    y = p(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y.view(torch.int16), whole.view(torch.int16))
+    tcfft.tune_cache_clear()
