@@ -151,7 +151,7 @@ def other_workloads(stream) -> dict:
             host = np.stack(xh) if split else xh
             xd = torch.from_numpy(host).cuda()
             yd = torch.empty_like(xd)
-            p = tcfft.Plan(dims, batch, precision=prec)
+            p = tcfft.Plan(dims, batch, precision=prec, flags=tcfft.FLAG_TUNE)
             p(xd, yd, stream=stream)
             dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
             npts = int(np.prod(dims)) * batch
@@ -172,7 +172,8 @@ def other_workloads(stream) -> dict:
                         "gflops": round(5.0 * n * math.log2(n) * batch / dt / 1e9, 1),
                         "gbs_alg": round(bpp * npts / dt / 1e9, 1),
                         "hbm_frac_alg": round(bpp * npts / dt / 1e9 / HBM_PEAK_GBS, 4),
-                        "passes": p.num_launches, "rel_l2_row0": err}
+                        "passes": p.num_launches, "choice": p.describe()["choice"],
+                        "rel_l2_row0": err}
             log(f"{key}: {out[key]}")
             del xd, yd, p
             torch.cuda.empty_cache()
@@ -247,8 +248,10 @@ def main():
         xs[n] = (x, tones)
         xd[n] = torch.from_numpy(x).to(dev)
         yd[n] = torch.empty_like(xd[n])
-        plans[n] = tcfft.Plan((n,), batch)
-        log(f"  plan {plans[n].describe()['passes']}")
+        # autotuned plan (tuning happens at plan creation, outside the timing)
+        plans[n] = tcfft.Plan((n,), batch, flags=tcfft.FLAG_TUNE)
+        d = plans[n].describe()
+        log(f"  plan choice={d['choice']} tuned_us={d['tuned_us']:.1f} {d['passes']}")
     torch.cuda.synchronize()
 
     def step():
@@ -287,6 +290,7 @@ def main():
     dk = plans[dom].describe()["passes"][0]
     kname = (f"row_kernel<{dk['L']}, {dk['radices'][0] if dk['radices'][0] != 16 else 1}, "
              f"{dk['NT']}, false>")
+    per[dom]["choice"] = plans[dom].describe()["choice"]
     achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),

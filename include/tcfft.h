@@ -198,8 +198,10 @@ typedef struct {
   size_t mem_budget_bytes; /* > 0: payload + workspace of all requests in flight */
   size_t arena_bytes;      /* workspace arena per slot; 0 = mem_budget_bytes / nslots */
   int use_graphs;          /* nonzero: each slot captures its grouped launches as a HIP graph
-                              once per kernel-variant sequence and replays it (descriptor
-                              tables are rewritten in device memory per batch) */
+                              once a kernel-variant sequence recurs, and replays it
+                              (descriptor tables are rewritten in device memory per batch) */
+  int batch_window_us;     /* while other slots are busy, hold a batch until its oldest
+                              request has waited this long (0 = dispatch at once) */
 } tcfft_server_config;
 
 typedef struct {

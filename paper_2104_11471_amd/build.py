@@ -18,6 +18,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no implicit multiply-add fusion: results depend only on the source,
+         # not on how a kernel body was inlined
+         "-ffp-contract=off",
          "-Wno-unused-command-line-argument"]
 UNITS = ["k_row.hip", "k_col_small.hip", "k_col_256.hip", "k_col_large.hip", "k_misc.hip",
          "registry.cpp", "tcfft.cpp", "serve.cpp"]

@@ -40,8 +40,11 @@ __device__ __forceinline__ uint32_t pack(float re, float im) {
   return __builtin_bit_cast(uint32_t, h);
 }
 
+// Complex product with its fused multiply-adds written out: the library is
+// built with -ffp-contract=off, so every kernel instantiation (single and
+// grouped launches) performs exactly these roundings and gives the same bits.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
 // Split hi+lo encoding of an FP32 value v: hi = fp16(v), lo = fp16((v - hi) * 2^11).

@@ -27,6 +27,8 @@ struct Job {
 // variants of a batch (owned by one stream / descriptor arena).
 struct GraphCache {
   std::map<std::string, void*> execs;  // hipGraphExec_t
+  std::map<std::string, int> seen;     // batches seen per sequence before capturing
+  int capture_after = 3;               // capture a sequence on its 3rd occurrence
   ~GraphCache();
 };
 

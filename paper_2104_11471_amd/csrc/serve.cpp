@@ -153,11 +153,19 @@ bool reap(tcfft_server_s* s) {
 }
 
 // Admits a FIFO prefix of the queue into idle slot `sl` and launches it.
+// While other slots keep the GPU busy, a batch is held back until its oldest
+// request has waited batch_window_us (so batches grow with the load); an idle
+// GPU takes whatever is queued at once.
 bool dispatch(tcfft_server_s* s, Slot& sl) {
   std::vector<Req> batch;
   size_t bytes = 0, arena_used = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->queue.empty()) return false;
+    if (s->busy_slots.load() > 0 && s->cfg.batch_window_us > 0 &&
+        (int)s->queue.size() < s->cfg.max_batch_jobs &&
+        now_ns() - s->queue.front().t_submit < (int64_t)s->cfg.batch_window_us * 1000)
+      return false;
     while (!s->queue.empty() && (int)batch.size() < s->cfg.max_batch_jobs) {
       const Req& q = s->queue.front();
       const size_t need = q.payload + q.ws;
@@ -228,12 +236,10 @@ tcfft_status request_sizes(tcfft_server_s* s, const tcfft_request& r, Req* q) {
   if (r.precision == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
   tcfft_status st = get_plan(s, r, &q->plan);
   if (st) return st;
-  int64_t dims[2] = {r.dims[0], r.rank == 2 ? r.dims[1] : 1};
-  char buf[16];
-  // validate the batch against the plan limits with the planner itself
-  const int n = tcfft_plan_dry_run(r.rank, dims, r.batch, r.dir, r.precision, 0, buf, sizeof buf);
-  if (n < 0) return (tcfft_status)(-n);
-  const int64_t pts = tcfft_internal_plan_points(q->plan) * r.batch;
+  // the plan validated the shape; the batch only has the per-plan point limit
+  const int64_t npts = tcfft_internal_plan_points(q->plan);
+  if (r.batch > ((int64_t)1 << 31) / npts) return TCFFT_ERR_UNSUPPORTED;
+  const int64_t pts = npts * r.batch;
   const size_t elt = r.precision == TCFFT_PREC_SPLIT_FP16 ? 8 : 4;
   q->payload = 2 * (size_t)pts * elt;
   q->ws = tcfft_internal_plan_ws_bytes(q->plan, r.batch);
@@ -249,7 +255,8 @@ int64_t tcfft_server_now_ns(void) { return now_ns(); }
 tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* cfg) {
   if (!out || !cfg) return TCFFT_ERR_INVALID_ARG;
   *out = nullptr;
-  if (cfg->nslots < 1 || cfg->nslots > 16 || cfg->max_batch_jobs < 1 || cfg->mem_budget_bytes == 0)
+  if (cfg->nslots < 1 || cfg->nslots > 16 || cfg->max_batch_jobs < 1 ||
+      cfg->mem_budget_bytes == 0 || cfg->batch_window_us < 0)
     return TCFFT_ERR_INVALID_ARG;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {

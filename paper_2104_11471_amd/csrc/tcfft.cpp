@@ -745,10 +745,17 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     }
     return TCFFT_OK;
   };
+  std::string sig;
+  bool use_graph = false;
   if (graphs && desc_arena) {
     // the captured launches depend only on the variant sequence and on the
-    // fixed header addresses, so one graph serves every batch of that shape
-    const std::string sig((const char*)keys.data(), keys.size() * sizeof(KernelKey));
+    // fixed header addresses, so one graph serves every batch of that shape;
+    // a sequence is captured only once it recurs (capture costs far more
+    // than a few launches)
+    sig.assign((const char*)keys.data(), keys.size() * sizeof(KernelKey));
+    use_graph = graphs->execs.count(sig) > 0 || ++graphs->seen[sig] >= graphs->capture_after;
+  }
+  if (use_graph) {
     auto it = graphs->execs.find(sig);
     if (it == graphs->execs.end()) {
       hipGraph_t graph = nullptr;
@@ -865,7 +872,7 @@ std::vector<Choice> candidates_base(const Desc& d) {
   for (int e1 = 4; e1 <= 11; ++e1) {  // two passes
     const int e2 = lg - e1;
     if (e2 < 4 || e2 > 11) continue;
-    for (int cmax : {64, 32}) {
+    for (int cmax : {64, 32, 16}) {
       Choice c;
       c.cmax = cmax;
       c.nf = 2;
@@ -945,9 +952,17 @@ tcfft_status choose(const Desc& d, Choice* ch, bool* tuned, double* tuned_us) {
   dt.batch = std::max<int64_t>(1, std::min<int64_t>(d.batch, ((int64_t)1 << 26) / npts));
   size_t bytes = 0;
   std::vector<PlanSpec> specs;
+  std::vector<std::string> seen;  // candidates that build the same kernels are timed once
   for (const Choice& c : cands) {
     PlanSpec ps;
     if (build_spec(dt, c, &ps) != TCFFT_OK) continue;
+    std::string k = describe(ps);
+    const size_t cut = k.find("\"choice\"");
+    const size_t pas = k.find("\"passes\"");
+    if (cut != std::string::npos && pas != std::string::npos) k.erase(cut, pas - cut);
+    k += std::to_string(ps.ch.chunk);
+    if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+    seen.push_back(k);
     bytes = std::max(bytes, ps.buf_bytes);
     specs.push_back(ps);
   }

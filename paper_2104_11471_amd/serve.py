@@ -21,7 +21,7 @@ lib = _tc.lib
 class ServerConfig(ctypes.Structure):
     _fields_ = [("nslots", ctypes.c_int), ("max_batch_jobs", ctypes.c_int),
                 ("mem_budget_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t),
-                ("use_graphs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("batch_window_us", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -77,8 +77,9 @@ def _request(rank, dims, batch, direction, precision, in_ptr=0, out_ptr=0, tag=0
 
 class Server:
     def __init__(self, nslots: int = 4, mem_budget_bytes: int = 16 << 30, max_batch_jobs: int = 256,
-                 arena_bytes: int = 0, use_graphs: bool = True):
-        cfg = ServerConfig(nslots, max_batch_jobs, mem_budget_bytes, arena_bytes, int(use_graphs))
+                 arena_bytes: int = 0, use_graphs: bool = True, batch_window_us: int = 100):
+        cfg = ServerConfig(nslots, max_batch_jobs, mem_budget_bytes, arena_bytes, int(use_graphs),
+                           int(batch_window_us))
         h = ctypes.c_void_p()
         st = lib.tcfft_server_create(ctypes.byref(h), ctypes.byref(cfg))
         if st != 0:
@@ -141,7 +142,9 @@ def shape_class(req) -> tuple:
 class PayloadPool:
     """Device-resident inputs and outputs per shape class, sized for the class's
     largest batch.  `slots` buffers per class; an output buffer is reused only
-    after the request that wrote it has completed."""
+    after the request that wrote it has completed.  Buffers are flat: a request
+    of batch b uses the first b*N points (2*b*N for split: hi plane then lo
+    plane) in the ABI layout of batch b (`view`)."""
 
     def __init__(self, requests, slots: int = 8, seed: int = 0):
         import torch
@@ -158,11 +161,20 @@ class PayloadPool:
                 x = np.stack(inputs.to_split(inputs.uniform_f64((b, *dims), seed + i)))
             else:
                 x = inputs.uniform((b, *dims), seed + i)
-            t = torch.from_numpy(x).cuda()
+            t = torch.from_numpy(x).cuda().reshape(-1)
             self.inp[k] = t
             self.out[k] = [torch.empty_like(t) for _ in range(slots)]
             self.free[k] = list(range(slots))
         torch.cuda.synchronize()
+
+    @staticmethod
+    def view(flat, k, b):
+        """The first request-sized part of a flat class buffer, shaped for batch b."""
+        rank, dims, prec = k
+        n = int(np.prod(dims))
+        if prec == "split":
+            return flat[: 2 * b * n * 2].view(2, b, *dims, 2)
+        return flat[: b * n * 2].view(b, *dims, 2)
 
     def nbytes(self) -> int:
         return sum(t.numel() * t.element_size() * (1 + self.slots) for t in self.inp.values())

@@ -112,7 +112,8 @@ def test_chunked_execution_is_bitwise_equal(dims, batch, chunk, tmp_path):
     tcfft.tune_cache_load(str(path))
     p = tcfft.Plan(dims, batch)
     assert p.describe()["choice"]["chunk"] == chunk
-    assert p.workspace_bytes < tcfft.Plan(dims, 1).workspace_bytes * batch
+    if len(dims) == 1:  # 2D plans have no workspace
+        assert p.workspace_bytes < tcfft.Plan(dims, 1).workspace_bytes * batch
     y = p(x)
     torch.cuda.synchronize()
     assert torch.equal(y.view(torch.int16), whole.view(torch.int16))

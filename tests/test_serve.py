@@ -33,12 +33,11 @@ def test_stream_results_equal_alone():
         r = byid[tag]
         k = serve.shape_class(r)
         p = tcfft.Plan(r.dims, r.batch, precision=k[2])
-        x = pool.inp[k][:, :r.batch] if k[2] == "split" else pool.inp[k][:r.batch]
-        x = x.contiguous()
+        x = serve.PayloadPool.view(pool.inp[k], k, r.batch)
         alone = p(x)
         torch.cuda.synchronize()
-        got = got[:, :r.batch] if k[2] == "split" else got[:r.batch]
-        assert torch.equal(got.contiguous().view(torch.int16), alone.view(torch.int16)), (tag, k)
+        got = serve.PayloadPool.view(got, k, r.batch)
+        assert torch.equal(got.view(torch.int16), alone.view(torch.int16)), (tag, k)
     srv.close()
 
 
