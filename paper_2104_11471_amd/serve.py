@@ -262,7 +262,15 @@ def summarize(recs, wall_s: float) -> dict:
                 "p99_us": round(float(np.percentile(a, 99)), 1),
                 "max_us": round(float(a.max()), 1), "n": int(a.size)} if a.size else {}
 
-    return {"requests": int(lat.size), "failed": int(len(recs) - lat.size),
+    # when did the slow requests arrive (relative to the first arrival)?
+    ok = [r for r in recs.values() if r.get("status") == 0 and r.get("t_done") is not None]
+    t_first = min(r["arrival"] for r in ok) if ok else 0
+    slow = sorted(((r["arrival"] - t_first) / 1e6, (r["t_done"] - r["arrival"]) / 1e3) for r in ok
+                  if (r["t_done"] - r["arrival"]) > 5000)
+    slow_info = {"n_over_5ms": len(slow),
+                 "first_arrival_ms": round(slow[0][0], 2) if slow else None,
+                 "last_arrival_ms": round(slow[-1][0], 2) if slow else None}
+    return {"requests": int(lat.size), "failed": int(len(recs) - lat.size), "slow": slow_info,
             "req_per_s": round(lat.size / wall_s, 1), "points_per_s": round(pts / wall_s, 1),
             "gflops": round(flop / wall_s / 1e9, 1), **pct(lat),
             "by_class": {k: pct(v) for k, v in sorted(by_class.items())}}

@@ -46,6 +46,13 @@ class TcfftError(RuntimeError):
 
 
 def _load() -> ctypes.CDLL:
+    # One HIP runtime per process: torch ships its own libamdhip64, and the
+    # streams and device pointers the binding passes come from it, so torch
+    # (when installed) is loaded first and libtcfft binds to that runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m "
                            "paper_2104_11471_amd.build` (there is no fallback path)")
