@@ -183,25 +183,38 @@ def other_workloads(stream) -> dict:
 def serving_leg(seconds: float) -> dict:
     """Poisson stream (20k req/s) of the mixed request population through the
     continuous-batching scheduler: p50/p99 latency and throughput.  Payloads
-    are pre-staged in device memory (at these rates they would exceed PCIe)."""
+    are pre-staged in device memory (at these rates they would exceed PCIe).
+    The main figures use immediate dispatch with direct grouped launches; the
+    same stream with HIP-graph replay and a 100 us batching window is reported
+    beside them."""
     from paper_2104_11471_amd import inputs, serve
     reqs = inputs.serving_stream(rate_hz=20000.0, duration_s=seconds, seed=0)
     pool = serve.PayloadPool(reqs, slots=12)
-    srv = serve.Server(nslots=4, mem_budget_bytes=24 << 30, max_batch_jobs=512)
-    srv.prepare({(r.rank, tuple(r.dims), -1, "split" if r.split else "fp16") for r in reqs})
-    # warm the kernels once with the first few requests
-    serve.run_stream(srv, reqs[:64], pool)
-    t0 = serve.now_ns()
-    recs, _ = serve.run_stream(srv, reqs, pool)
-    wall = (serve.now_ns() - t0) / 1e9
-    out = serve.summarize(recs, wall)
-    st = srv.stats()
-    out.update({"offered_req_per_s": 20000.0, "seconds": seconds, "slots": 4,
-                "batches": st["batches"], "max_batch_jobs": st["max_batch_jobs"],
-                "max_inflight_bytes": st["max_inflight_bytes"],
-                "payload_pool_bytes": pool.nbytes()})
-    srv.close()
-    return out
+    shapes = {(r.rank, tuple(r.dims), -1, "split" if r.split else "fp16") for r in reqs}
+
+    def one(use_graphs, window):
+        srv = serve.Server(nslots=4, mem_budget_bytes=24 << 30, max_batch_jobs=512,
+                           use_graphs=use_graphs, batch_window_us=window)
+        srv.prepare(shapes)
+        serve.run_stream(srv, reqs[:64], pool)  # warm the kernels
+        t0 = serve.now_ns()
+        recs, _ = serve.run_stream(srv, reqs, pool)
+        wall = (serve.now_ns() - t0) / 1e9
+        out = serve.summarize(recs, wall)
+        st = srv.stats()
+        out.update({"offered_req_per_s": 20000.0, "seconds": seconds, "slots": 4,
+                    "graphs": use_graphs, "batch_window_us": window,
+                    "batches": st["batches"], "max_batch_jobs": st["max_batch_jobs"],
+                    "max_inflight_bytes": st["max_inflight_bytes"],
+                    "payload_pool_bytes": pool.nbytes()})
+        srv.close()
+        return out
+
+    main = one(False, 0)
+    alt = one(True, 100)
+    main["graphs_window100"] = {k: alt[k] for k in ("p50_us", "p99_us", "max_us", "req_per_s",
+                                                    "batches", "max_batch_jobs")}
+    return main
 
 
 def main():

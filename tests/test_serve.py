@@ -6,16 +6,19 @@ from paper_2104_11471_amd import inputs
 
 
 @pytest.mark.gpu
-def test_stream_results_equal_alone():
+@pytest.mark.parametrize("graphs,window", [(False, 0), (True, 100)])
+def test_stream_results_equal_alone(graphs, window):
     """A short Poisson stream of the mixed population: every request completes,
-    and sampled results are bitwise the results of the same request run alone."""
+    and sampled results are bitwise the results of the same request run alone,
+    with direct launches and with HIP-graph replay plus a batching window."""
     import torch
     from paper_2104_11471_amd import serve, tcfft
     tcfft.tune_cache_clear()
     reqs = inputs.serving_stream(rate_hz=20000, duration_s=0.1, seed=3)
     # keep 2^20 requests few to bound the test's memory
     pool = serve.PayloadPool(reqs, slots=16)
-    srv = serve.Server(nslots=4, mem_budget_bytes=8 << 30, max_batch_jobs=128)
+    srv = serve.Server(nslots=4, mem_budget_bytes=8 << 30, max_batch_jobs=128,
+                       use_graphs=graphs, batch_window_us=window)
     srv.prepare({(r.rank, tuple(r.dims), -1, "split" if r.split else "fp16") for r in reqs})
     rng = np.random.default_rng(0)
     check = set(rng.choice([r.rid for r in reqs], size=min(40, len(reqs)), replace=False).tolist())
