@@ -120,6 +120,22 @@ tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream
 tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
                              int njobs, void* stream);
 
+/*
+ * Runs only the first `npasses` passes of a multi-pass FP16 or split plan and
+ * writes that pass's result to `out` (used to check the intermediate against
+ * the decomposition of Sec. 2.1, Eq. 3).  After pass 1 of a long 1D plan with
+ * first pass length N1 and M = N / N1, transform b holds at b*N + m*N1 + k1
+ *     2^-s1 * W_N^{m k1} * sum_{n1 < N1} x[b][n1*M + m] * W_N1^{n1 k1},
+ * with s1 the pass's scale exponent (tcfft_plan_describe, "passes"[0].scale);
+ * after the row pass of a 2D plan it holds the row transforms in natural
+ * order.  npasses equal to the plan's pass count is tcfft_exec.  `in` and
+ * `out` must differ.  Errors: as tcfft_exec;
+ * INVALID_ARG for npasses outside [1, passes] or in == out; UNSUPPORTED for
+ * the FP32 comparator.
+ */
+tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
+                               void* stream);
+
 /* Releases the plan and its device memory (synchronises the device first).
  * NULL is accepted.  Errors: none besides INTERNAL. */
 tcfft_status tcfft_plan_destroy(tcfft_plan plan);

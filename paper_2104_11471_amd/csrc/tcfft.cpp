@@ -550,9 +550,13 @@ tcfft_status exec_r2(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) 
   return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
 }
 
-tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+// Runs the plan's passes (the first `npasses` of them when npasses >= 0, the
+// last of those writing to `out`).
+tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s,
+                       int npasses = -1) {
   const PlanSpec& ps = p->spec;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) return exec_r2(p, in, out, s);
+  const int np = npasses < 0 ? (int)p->dp.size() : npasses;
   const int64_t B = ps.d.batch;
   // chunked execution of multi-pass plans: every pass of a chunk before the
   // next chunk, the workspace region reused, so the intermediate of a chunk
@@ -568,7 +572,9 @@ tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s
       cin = (const uint32_t*)in + b0 * ps.npts;
       cout = (uint32_t*)out + b0 * ps.npts;
     }
-    for (const DevPass& dpp : p->dp) {
+    for (int i = 0; i < np; ++i) {
+      DevPass dpp = p->dp[i];
+      if (i == np - 1) dpp.spec.dst = 1;
       int64_t grid = 0;
       KParams kp = make_kparams(p, dpp, cin, cout, nb, p->ws, &grid);
       void* args[] = {&kp};
@@ -1052,6 +1058,15 @@ tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream
   if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
   return exec_impl(plan, in, out, (hipStream_t)stream);
+}
+
+tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
+                               void* stream) {
+  if (!plan || !in || !out || in == out) return TCFFT_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
+  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  if (npasses < 1 || npasses > (int)plan->dp.size()) return TCFFT_ERR_INVALID_ARG;
+  return exec_impl(plan, in, out, (hipStream_t)stream, npasses);
 }
 
 tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,

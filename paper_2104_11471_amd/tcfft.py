@@ -30,8 +30,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "
 
 # every symbol include/tcfft.h declares
 EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", "tcfft_exec_many",
-           "tcfft_plan_destroy", "tcfft_plan_scale_log2", "tcfft_plan_buffer_bytes",
-           "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
+           "tcfft_exec_passes", "tcfft_plan_destroy", "tcfft_plan_scale_log2",
+           "tcfft_plan_buffer_bytes", "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
            "tcfft_plan_dry_run", "tcfft_status_string", "tcfft_version", "tcfft_tune_candidates",
            "tcfft_tune_cache_size", "tcfft_tune_cache_save", "tcfft_tune_cache_load",
            "tcfft_tune_cache_clear", "tcfft_server_create", "tcfft_server_prepare",
@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_plan_2d.argtypes = [P(vp), i64, i64, i64]
     lib.tcfft_exec.argtypes = [vp, vp, vp, vp]
     lib.tcfft_exec_many.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
+    lib.tcfft_exec_passes.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.tcfft_plan_destroy.argtypes = [vp]
     lib.tcfft_plan_scale_log2.argtypes = [vp]
     lib.tcfft_plan_buffer_bytes.argtypes = [vp]
@@ -92,8 +93,9 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_tune_cache_clear.argtypes = []
     lib.tcfft_tune_cache_clear.restype = None
     for name in ("tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec",
-                 "tcfft_exec_many", "tcfft_plan_destroy", "tcfft_plan_scale_log2",
-                 "tcfft_plan_num_launches", "tcfft_plan_describe", "tcfft_plan_dry_run"):
+                 "tcfft_exec_many", "tcfft_exec_passes", "tcfft_plan_destroy",
+                 "tcfft_plan_scale_log2", "tcfft_plan_num_launches", "tcfft_plan_describe",
+                 "tcfft_plan_dry_run"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -235,6 +237,21 @@ class Plan:
         self._check(out, "output")
         s = stream if stream is not None else torch.cuda.current_stream(x.device)
         self.exec_raw(x.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def run_passes(self, x, npasses: int, out=None, stream=None):
+        """The first `npasses` passes only (the intermediate of Eq. 3)."""
+        import torch
+        self._check(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(out, "output")
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        st = lib.tcfft_exec_passes(self._h, ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), int(npasses),
+                                   ctypes.c_void_p(s.cuda_stream))
+        if st != 0:
+            raise TcfftError(st, "tcfft_exec_passes")
         return out
 
     def close(self):

@@ -133,6 +133,7 @@ def test_null_arguments(tc):
     assert lib.tcfft_plan_num_launches(None) == -1
     assert lib.tcfft_exec_many(None, None, None, -1, None) == 1
     assert lib.tcfft_exec_many(None, None, None, 0, None) == 0
+    assert lib.tcfft_exec_passes(None, None, None, 1, None) == 1
     h = ctypes.c_void_p()
     assert lib.tcfft_plan_create(ctypes.byref(h), 3, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
     assert lib.tcfft_plan_create(None, 1, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1

@@ -129,3 +129,92 @@ def test_tone_rows(tc):
         assert abs(abs(y[r, f]) - n) / n < 5e-3
         off = np.delete(np.abs(y[r]) ** 2, f).sum() / (n * n)
         assert off < 1e-4
+
+
+def _pass1_reference(xc, n1):
+    """Eq. 3 per-pass invariant of the four-step split N = N1 * M: pass 1 holds
+    Z[m][k1] = W_N^{m k1} * DFT_N1 over n1 of x[n1 M + m] (oracle sub-DFTs,
+    FP64 twiddles)."""
+    b, n = xc.shape
+    m = n // n1
+    sub = np.ascontiguousarray(xc.reshape(b, n1, m).transpose(0, 2, 1))  # [b][m][n1]
+    z = oracle.fft(sub.reshape(b * m, n1), -1).reshape(b, m, n1)
+    mm = np.arange(m, dtype=np.int64)[:, None]
+    kk = np.arange(n1, dtype=np.int64)[None, :]
+    tw = np.exp(-2j * np.pi * ((mm * kk) % n) / n)
+    return z * tw
+
+
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("n,batch", [(1 << 16, 3), (1 << 20, 2), (1 << 23, 1)])
+def test_pass1_intermediate(tc, n, batch, prec):
+    """The first pass of a multi-pass plan alone: its output equals the oracle's
+    N1-point sub-DFTs times W_N twiddles, transposed to [m][k1] (Eq. 3)."""
+    import torch
+    log(f"case pass1 n={n} batch={batch} prec={prec}")
+    if prec == "split":
+        x = inputs.to_split(inputs.uniform_f64((batch, n), 5))
+        host = np.stack([x[0], x[1]])
+        tol = SPLIT_TOL
+    else:
+        x = inputs.uniform((batch, n), 5)
+        host = x
+        tol = FP16_TOL
+    p = tc.Plan((n,), batch, precision=prec)
+    d = p.describe()
+    assert len(d["passes"]) >= 2
+    n1 = d["passes"][0]["L"]
+    s1 = d["passes"][0]["scale"]
+    t = torch.from_numpy(np.ascontiguousarray(host)).cuda()
+    out = p.run_passes(t, 1)
+    torch.cuda.synchronize()
+    y = out.cpu().numpy().astype(np.float64)
+    if prec == "split":
+        z = (y[0, ..., 0] + 2.0 ** -11 * y[1, ..., 0]) + 1j * (y[0, ..., 1] + 2.0 ** -11 * y[1, ..., 1])
+    else:
+        z = y[..., 0] + 1j * y[..., 1]
+    z = z.reshape(batch, n // n1, n1) * 2.0 ** s1
+    from tests.gpu_util import to_complex
+    ref = _pass1_reference(to_complex(x).reshape(batch, n), n1)
+    e = np.linalg.norm((z - ref).reshape(batch, -1), axis=1) / np.linalg.norm(
+        ref.reshape(batch, -1), axis=1)
+    log(f"  N1={n1} s1={s1} max rel L2 = {e.max():.3e}")
+    assert e.max() <= tol
+    # all passes through the same entry point is the whole transform
+    full = p.run_passes(t, len(d["passes"]))
+    ref_full = p(t)
+    torch.cuda.synchronize()
+    assert torch.equal(full.view(torch.int16), ref_full.view(torch.int16))
+
+
+def test_2d_row_pass_intermediate(tc):
+    """The row pass of a 2D plan alone: natural-order row transforms."""
+    import torch
+    nx, ny, batch = 64, 512, 3
+    x = inputs.uniform((batch, nx, ny), 6)
+    p = tc.Plan((nx, ny), batch)
+    s1 = p.describe()["passes"][0]["scale"]
+    t = torch.from_numpy(x).cuda()
+    y = p.run_passes(t, 1).cpu().numpy().astype(np.float64)
+    z = (y[..., 0] + 1j * y[..., 1]) * 2.0 ** s1
+    from tests.gpu_util import to_complex
+    ref = oracle.fft(to_complex(x).reshape(batch * nx, ny), -1).reshape(batch, nx, ny)
+    e = np.linalg.norm((z - ref).reshape(batch * nx, -1), axis=1) / np.linalg.norm(
+        ref.reshape(batch * nx, -1), axis=1)
+    assert e.max() <= FP16_TOL
+
+
+@pytest.mark.parametrize("dims", [(4096,), (1 << 20,), (256, 256)])
+def test_parseval_on_gpu_output(tc, dims):
+    """Parseval: N * sum|x|^2 = sum|X|^2 per transform, on the GPU result
+    (2^S restored), within the FP16 storage error."""
+    batch = 4
+    x = inputs.uniform((batch, *dims), 9)
+    p = tc.Plan(dims, batch)
+    y = run_plan(p, x)
+    from tests.gpu_util import to_complex
+    xc = to_complex(x).reshape(batch, -1)
+    n = xc.shape[1]
+    lhs = n * np.sum(np.abs(xc) ** 2, axis=1)
+    rhs = np.sum(np.abs(y.reshape(batch, -1)) ** 2, axis=1)
+    assert np.all(np.abs(rhs - lhs) / lhs <= 2 * FP16_TOL)
