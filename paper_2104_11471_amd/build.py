@@ -21,6 +21,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no implicit multiply-add fusion: results depend only on the source,
          # not on how a kernel body was inlined
          "-ffp-contract=off",
+         # matrix-core results go straight to VGPRs (no accumulator-register
+         # copies: the kernels consume every MFMA result on the vector ALU)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-command-line-argument"]
 UNITS = ["k_row.hip", "k_col_small.hip", "k_col_256.hip", "k_col_large.hip", "k_misc.hip",
          "registry.cpp", "tcfft.cpp", "serve.cpp"]

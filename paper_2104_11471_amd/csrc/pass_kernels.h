@@ -365,6 +365,124 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
   }
 }
 
+// Whether the radix-R0 stage and the first radix-16 stage of a row pass run
+// fused in registers (R0 in {2, 4}, at least two radix-16 stages, low-index
+// quads, and whole super-quads per wave; see row_stage_fused).
+template <class G>
+struct RowFused {
+  static constexpr int P = G::L / (16 * G::R0);  // digit stride of the first radix-16 stage
+  static constexpr int NSQ = G::PTS / (64 * G::R0);
+  static constexpr int ITF = NSQ / (16 * G::NW);
+  static constexpr bool value = (G::R0 == 2 || G::R0 == 4) && G::S >= 2 && P >= 4 &&
+                                ITF >= 1 && ITF * 16 * G::NW == NSQ;
+};
+
+// Radix-R0 stage fused with the first radix-16 stage (a radix-16*R0 block per
+// column, Eq. 3 applied twice without an exchange in between).  A lane owns a
+// super-quad: 4 adjacent low indices lo0..lo0+3 (16-byte accesses) of one line,
+// rows m = 4g..4g+3 of the radix-16 digit and all R0 values of the radix-R0
+// digit.  It runs the R0-point butterflies on the vector ALU, multiplies by
+// W_L^{k (m P + lo)}, rounds once to FP16, and feeds the results as the B
+// operands of R0 matrix-core DFTs (one per radix-R0 output k), whose results
+// take the twiddle W_{16P}^{k1 lo} and go to LDS at the positions the unfused
+// first radix-16 stage writes.
+template <class G, bool SPLIT>
+__device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds, int valid,
+                                                int64_t g0, const FOps& f) {
+  constexpr int L = G::L, R0 = G::R0;
+  using F = RowFused<G>;
+  constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
+  uint32_t* ldsl = lds + G::PTS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  // W_L^{k (4g+i) P} (scaled by the radix-R0 stage scale) and W_L^{k t}
+  float2 wm[R0][4], bt[R0][4];
+#pragma unroll
+  for (int k = 1; k < R0; ++k)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float2 w = kp.tw[k * (4 * g + i) * P];
+      w.x *= kp.r0scale;
+      w.y *= kp.r0scale;
+      wm[k][i] = w;
+      bt[k][i] = kp.tw[k * i];
+    }
+  const TwB B = load_twb(kp.tw, g, R0);  // W_{16P}^{(4g+j) t} = W_L^{(4g+j) t R0}
+#pragma unroll
+  for (int it = 0; it < ITF; ++it) {
+    const int sq = (wave * ITF + it) * 16 + c16;
+    const int tau = sq / (P / 4);
+    const int lo0 = 4 * (sq % (P / 4));
+    const int taul = (G::TPB > 1 && tau >= valid) ? 0 : tau;  // past the batch: line 0
+    u4 hh[R0][4], ll[R0][4];
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = taul * L + d * P0 + (4 * g + i) * P + lo0;
+        hh[d][i] = gld4(kp.in + g0 + p);
+        if constexpr (SPLIT) ll[d][i] = gld4(kp.in + kp.in_plane + g0 + p);
+        else ll[d][i] = u4{0, 0, 0, 0};
+      }
+    float2 at[R0][4];  // W_L^{k (lo0 + t)}
+#pragma unroll
+    for (int k = 1; k < R0; ++k) {
+      const float2 a = kp.tw[k * lo0];
+      at[k][0] = a;
+#pragma unroll
+      for (int t = 1; t < 4; ++t) at[k][t] = cmul(a, bt[k][t]);
+    }
+    float2 a16[4];  // W_{16P}^{(4g+j) lo0}
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a16[j] = kp.tw[(4 * g + j) * lo0 * R0];
+    uint32_t oh[R0][4][4], ol[R0][4][4];  // [k][t][j]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      u4 xh[R0], xl[R0];  // B operands: rows i of the radix-16 digit, per k
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float2 v[R0];
+#pragma unroll
+        for (int d = 0; d < R0; ++d) v[d] = value<SPLIT>(hh[d][i][t], ll[d][i][t]);
+        small_dft<R0>(v, kp.sgn);
+        v[0].x *= kp.r0scale;
+        v[0].y *= kp.r0scale;
+#pragma unroll
+        for (int k = 1; k < R0; ++k) v[k] = cmul(v[k], cmul(wm[k][i], at[k][t]));
+#pragma unroll
+        for (int k = 0; k < R0; ++k) {
+          uint32_t eh = 0, el = 0;
+          emit<SPLIT>(v[k].x, v[k].y, eh, el);
+          xh[k][i] = eh;
+          xl[k][i] = el;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R0; ++k) {
+        f4 yr, yi;
+        dft_tile<SPLIT>(xh[k], xl[k], f, yr, yi);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float2 z = make_float2(yr[j], yi[j]);
+          z = cmul(z, t == 0 ? a16[j] : cmul(a16[j], B.b[j][t - 1]));
+          uint32_t eh = 0, el = 0;
+          emit<SPLIT>(z.x, z.y, eh, el);
+          oh[k][t][j] = eh;
+          ol[k][t][j] = el;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R0; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = tau * L + k * P0 + (4 * g + j) * P + lo0;
+        lds_st4(lds, p, u4{oh[k][0][j], oh[k][1][j], oh[k][2][j], oh[k][3][j]});
+        if constexpr (SPLIT) lds_st4(ldsl, p, u4{ol[k][0][j], ol[k][1][j], ol[k][2][j], ol[k][3][j]});
+      }
+  }
+}
+
 template <class G, int E, bool SPLIT>
 __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds, int valid,
                                                 int64_t g0, const FOps& f) {
@@ -385,7 +503,11 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
   const int valid = rem < G::TPB ? (int)rem : G::TPB;
   const int64_t g0 = t0 * L;
   const FOps f = load_fops<SPLIT>(kp.fimg);
-  if constexpr (R0 > 1) {
+  if constexpr (RowFused<G>::value) {
+    row_stage_fused<G, SPLIT>(kp, lds, valid, g0, f);
+    __syncthreads();
+    row_stages_from<G, G::S - 2, SPLIT>(kp, lds, valid, g0, f);
+  } else if constexpr (R0 > 1) {
     row_stage_r0<G, SPLIT>(kp, lds, valid, g0);
     __syncthreads();
     row_stages_from<G, G::S - 1, SPLIT>(kp, lds, valid, g0, f);
@@ -629,6 +751,112 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
   }
 }
 
+// Column-pass counterpart of row_stage_fused: a lane owns 4 adjacent columns
+// c..c+3 (16-byte accesses) at one low index lo of the first radix-16 stage,
+// rows m = 4g..4g+3 of that stage's digit and all R0 values of the radix-R0
+// digit; both stages run in registers and the result goes to LDS.
+template <class G>
+struct ColFused {
+  static constexpr int P = G::L / (16 * G::R0);
+  static constexpr int NSQ = G::PTS / (64 * G::R0);
+  static constexpr int ITF = NSQ / (16 * G::NW);
+  static constexpr bool value = (G::R0 == 2 || G::R0 == 4) && G::S >= 2 && G::C >= 4 &&
+                                ITF >= 1 && ITF * 16 * G::NW == NSQ;
+};
+
+template <class G, bool SPLIT>
+__device__ __forceinline__ void col_stage_fused(const KParams& kp, uint32_t* lds, const ColCtx& cx,
+                                                const FOps& f) {
+  constexpr int L = G::L, R0 = G::R0, C = G::C;
+  using F = ColFused<G>;
+  constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
+  uint32_t* ldsl = lds + G::PTS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  float2 wm[R0][4];  // W_L^{k (4g+i) P}, scaled by the radix-R0 stage scale
+#pragma unroll
+  for (int k = 1; k < R0; ++k)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float2 w = kp.tw[k * (4 * g + i) * P];
+      w.x *= kp.r0scale;
+      w.y *= kp.r0scale;
+      wm[k][i] = w;
+    }
+#pragma unroll
+  for (int it = 0; it < ITF; ++it) {
+    const int sq = (wave * ITF + it) * 16 + c16;
+    const int c = 4 * (sq % (C / 4));
+    const int lo = sq / (C / 4);  // in [0, P)
+    u4 hh[R0][4], ll[R0][4];
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t a = cx.in_base + (int64_t)(d * P0 + (4 * g + i) * P + lo) * kp.s_in + c;
+        hh[d][i] = gld4(kp.in + a);
+        if constexpr (SPLIT) ll[d][i] = gld4(kp.in + kp.in_plane + a);
+        else ll[d][i] = u4{0, 0, 0, 0};
+      }
+    // the 4 columns share (row, lo): one radix-R0 twiddle per (k, i), one
+    // radix-16 twiddle per output row
+    float2 w[R0][4];
+#pragma unroll
+    for (int k = 1; k < R0; ++k) {
+      const float2 a = kp.tw[k * lo];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[k][i] = cmul(wm[k][i], a);
+    }
+    float2 a16[4];  // W_{16P}^{(4g+j) lo}
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a16[j] = kp.tw[(4 * g + j) * lo * R0];
+    uint32_t oh[R0][4][4], ol[R0][4][4];  // [k][t][j]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      u4 xh[R0], xl[R0];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float2 v[R0];
+#pragma unroll
+        for (int d = 0; d < R0; ++d) v[d] = value<SPLIT>(hh[d][i][t], ll[d][i][t]);
+        small_dft<R0>(v, kp.sgn);
+        v[0].x *= kp.r0scale;
+        v[0].y *= kp.r0scale;
+#pragma unroll
+        for (int k = 1; k < R0; ++k) v[k] = cmul(v[k], w[k][i]);
+#pragma unroll
+        for (int k = 0; k < R0; ++k) {
+          uint32_t eh = 0, el = 0;
+          emit<SPLIT>(v[k].x, v[k].y, eh, el);
+          xh[k][i] = eh;
+          xl[k][i] = el;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R0; ++k) {
+        f4 yr, yi;
+        dft_tile<SPLIT>(xh[k], xl[k], f, yr, yi);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float2 z = cmul(make_float2(yr[j], yi[j]), a16[j]);
+          uint32_t eh = 0, el = 0;
+          emit<SPLIT>(z.x, z.y, eh, el);
+          oh[k][t][j] = eh;
+          ol[k][t][j] = el;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R0; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = (k * P0 + (4 * g + j) * P + lo) * C + c;
+        lds_st4(lds, p, u4{oh[k][0][j], oh[k][1][j], oh[k][2][j], oh[k][3][j]});
+        if constexpr (SPLIT) lds_st4(ldsl, p, u4{ol[k][0][j], ol[k][1][j], ol[k][2][j], ol[k][3][j]});
+      }
+  }
+}
+
 template <class G, int E, bool SPLIT, bool XTW, bool TSTORE>
 __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds, const ColCtx& cx,
                                                 const FOps& f) {
@@ -652,7 +880,11 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
   else
     cx.out_base = cx.outer * kp.out_outer + (cx.i0 / kp.q) * kp.qstride + (cx.i0 % kp.q);
   const FOps f = load_fops<SPLIT>(kp.fimg);
-  if constexpr (R0 > 1) {
+  if constexpr (ColFused<G>::value) {
+    col_stage_fused<G, SPLIT>(kp, lds, cx, f);
+    __syncthreads();
+    col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+  } else if constexpr (R0 > 1) {
     col_stage_r0<G, SPLIT>(kp, lds, cx);
     __syncthreads();
     col_stages_from<G, G::S - 1, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
