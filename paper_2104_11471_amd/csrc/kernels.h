@@ -28,12 +28,14 @@ struct KParams {
   int32_t xbits;
   uint32_t xmask;          // M - 1
   int64_t xdiv;
+  // log2 of blocks, q and xdiv (all powers of two)
+  int32_t blocks_log2, q_log2, xdiv_log2, reserved;
 };
 
 // The same struct is read by host code (x86-64) and, in grouped launches, by
 // device code from a table in device memory: both ABIs lay it out alike
 // (8-byte pointers and int64_t, 4-byte float/int32, natural alignment).
-static_assert(sizeof(KParams) == 152, "KParams layout changed: host and device must agree");
+static_assert(sizeof(KParams) == 168, "KParams layout changed: host and device must agree");
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).

@@ -603,9 +603,10 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
   }
 }
 
-// Extra inter-pass twiddle W_M^{ci * k} (two-level table, FP32).
-__device__ __forceinline__ float2 xtwiddle(const KParams& kp, int64_t ci, int64_t k) {
-  const uint32_t e = (uint32_t)(((uint64_t)ci * (uint64_t)k) & kp.xmask);
+// Extra inter-pass twiddle W_M^{ci * k} (two-level table, FP32).  M is a power
+// of two below 2^32, so the exponent needs only the low 32 bits of ci * k.
+__device__ __forceinline__ float2 xtwiddle(const KParams& kp, uint32_t ci, uint32_t k) {
+  const uint32_t e = (ci * k) & kp.xmask;
   const float2 a = kp.xtw_lo[e & ((1u << kp.xbits) - 1u)];
   const float2 b = kp.xtw_hi[e >> kp.xbits];
   return cmul(a, b);
@@ -660,17 +661,17 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
 #pragma unroll
         for (int t = 0; t < 4; ++t) w[t][j] = v;
       } else if constexpr (XTW) {
-        const int64_t k = restl + (L / 16) * (4 * g + j);  // natural output index
+        const uint32_t k = (uint32_t)(restl + (L / 16) * (4 * g + j));  // natural output index
+        const uint32_t ci = (uint32_t)(cx.i0 + c);
         if (kp.xdiv == 1) {
-          const float2 a = xtwiddle(kp, cx.i0 + c, k);
+          // W_M^{(ci + t) k} = W_M^{ci k} * (W_M^k)^t
+          const float2 a = xtwiddle(kp, ci, k);
           const float2 b1 = kp.xtw_lo[k];  // W_M^k (k < L <= 2^xbits)
-          const float2 b2 = cmul(b1, b1);
           w[0][j] = a;
-          w[1][j] = cmul(a, b1);
-          w[2][j] = cmul(a, b2);
-          w[3][j] = cmul(a, cmul(b2, b1));
+#pragma unroll
+          for (int t = 1; t < 4; ++t) w[t][j] = cmul(w[t - 1][j], b1);
         } else {
-          const float2 a = xtwiddle(kp, (cx.i0 + c) / kp.xdiv, k);  // same column group
+          const float2 a = xtwiddle(kp, ci >> kp.xdiv_log2, k);  // same column group
 #pragma unroll
           for (int t = 0; t < 4; ++t) w[t][j] = a;
         }
@@ -872,13 +873,13 @@ template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
 __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = ColGeom<L, R0, C, NT>;
   ColCtx cx;
-  cx.outer = wg / kp.blocks;
-  cx.i0 = (wg % kp.blocks) * C;
+  cx.outer = wg >> kp.blocks_log2;
+  cx.i0 = (wg & (kp.blocks - 1)) * C;
   cx.in_base = cx.outer * kp.in_outer + cx.i0;
   if constexpr (TSTORE)
     cx.out_base = cx.outer * kp.out_outer + cx.i0 * L;
   else
-    cx.out_base = cx.outer * kp.out_outer + (cx.i0 / kp.q) * kp.qstride + (cx.i0 % kp.q);
+    cx.out_base = cx.outer * kp.out_outer + (cx.i0 >> kp.q_log2) * kp.qstride + (cx.i0 & (kp.q - 1));
   const FOps f = load_fops<SPLIT>(kp.fimg);
   if constexpr (ColFused<G>::value) {
     col_stage_fused<G, SPLIT>(kp, lds, cx, f);

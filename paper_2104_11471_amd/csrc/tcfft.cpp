@@ -155,6 +155,8 @@ tcfft_status add_col_pass(PlanSpec& ps, int L, int64_t inner, int64_t outer, int
   p.s_in = inner;
   p.s_out = s_out;
   p.blocks = inner / p.key.C;
+  // the kernels divide by these with shifts
+  if (!is_pow2(p.blocks) || !is_pow2(q) || !is_pow2(xdiv)) return TCFFT_ERR_INTERNAL;
   p.in_outer = in_outer;
   p.out_outer = out_outer;
   p.q = q;
@@ -526,6 +528,9 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.xbits = dpp.xbits;
   kp.xmask = (uint32_t)(sp.xmod > 0 ? sp.xmod - 1 : 0);
   kp.xdiv = sp.xdiv;
+  kp.blocks_log2 = sp.blocks > 0 ? ilog2(sp.blocks) : 0;
+  kp.q_log2 = ilog2(sp.q);
+  kp.xdiv_log2 = ilog2(sp.xdiv);
   return kp;
 }
 
