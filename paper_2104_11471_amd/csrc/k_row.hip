@@ -8,9 +8,11 @@ namespace tcfft {
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true>;                          \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true>;                      \
+      out->persistent = RowPipe<RowGeom<L_, R_, N_>, true>::value;                   \
     } else {                                                                        \
       out->single = (KernelFn)row_kernel<L_, R_, N_, false>;                         \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, false>;                     \
+      out->persistent = RowPipe<RowGeom<L_, R_, N_>, false>::value;                  \
     }                                                                                \
     return true;                                                                     \
   }

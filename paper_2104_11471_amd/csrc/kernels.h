@@ -67,6 +67,7 @@ typedef void (*MultiFn)(const GroupHdr*);
 struct KernelFns {
   KernelFn single = nullptr;
   MultiFn multi = nullptr;
+  bool persistent = false;  // `single` strides over tiles: any grid up to the tile count works
 };
 
 // Looks up the compiled variant for `key`; false when it is not compiled.

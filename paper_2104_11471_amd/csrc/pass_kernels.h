@@ -237,9 +237,37 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
 // Radix-16 stage with digit stride P.  SRCG: read HBM (first stage), else LDS.
 // P > 1: writes LDS (twiddled); P == 1: last stage, writes HBM in natural order.
 // Loads of a stage (data, then twiddles) are all issued before the first use.
-template <class G, int P, bool SRCG, bool SPLIT>
+// HBM loads of a first radix-16 stage with P > 1 (rows 4g..4g+3 of each quad,
+// 16 bytes along the low index), issued ahead of its compute by the pipelined
+// row kernel.
+template <class G>
+struct Row16Regs {
+  u4 h[G::QPW][4], l[G::QPW][4];
+};
+template <class G, int P, bool SPLIT>
+__device__ __forceinline__ void row_stage16_load(const KParams& kp, int valid, int64_t g0,
+                                                 Row16Regs<G>& r) {
+  constexpr int L = G::L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+  for (int qq = 0; qq < G::QPW; ++qq) {
+    const int col0 = 4 * c16 + 64 * (wave * G::QPW + qq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int p = row_pos_t<L, P>(col0, 4 * g + i);
+      if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
+      r.h[qq][i] = gld4(kp.in + g0 + p);
+      if constexpr (SPLIT) r.l[qq][i] = gld4(kp.in + kp.in_plane + g0 + p);
+      else r.l[qq][i] = u4{0, 0, 0, 0};
+    }
+  }
+}
+
+template <class G, int P, bool SRCG, bool SPLIT, bool PRE = false>
 __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, int valid,
-                                            int64_t g0, const FOps& f) {
+                                            int64_t g0, const FOps& f,
+                                            const Row16Regs<G>* pre = nullptr) {
   constexpr int L = G::L, R0 = G::R0, S = G::S;
   constexpr int TM = P > 1 ? L / (16 * P) : 1;  // W_{16P}^e = W_L^{e TM}
   uint32_t* ldsl = lds + G::PTS;
@@ -258,7 +286,10 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int p = row_pos_t<L, P>(col0, 4 * g + i);
-        if constexpr (SRCG) {
+        if constexpr (PRE) {
+          rh[i] = pre->h[qq][i];
+          rl[i] = pre->l[qq][i];
+        } else if constexpr (SRCG) {
           if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
           rh[i] = gld4(kp.in + g0 + p);
           if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + g0 + p);
@@ -266,7 +297,7 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
           rh[i] = lds_ld4(lds, p);
           if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, p);
         }
-        if constexpr (!SPLIT) rl[i] = u4{0, 0, 0, 0};
+        if constexpr (!SPLIT && !PRE) rl[i] = u4{0, 0, 0, 0};
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -520,10 +551,56 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
   }
 }
 
+// Whether a row pass runs as a pipelined persistent kernel: split data (two LDS
+// planes, so one workgroup per CU) whose first stage is radix-16 from HBM with
+// P > 1, followed by at least one LDS stage.  With nothing else resident, the
+// workgroup overlaps its own next loads with its LDS stages.  FP16 passes keep
+// two workgroups per CU that overlap each other at least as well; passes with
+// a fused radix-2/4 first stage measured slower with the prefetch (or ran out
+// of registers).
+template <class G, bool SPLIT>
+struct RowPipe {
+  static constexpr bool value =
+      SPLIT && G::NT == 256 && !RowFused<G>::value && G::R0 == 1 && G::S >= 2;
+};
+
+// Pipelined persistent row pass: workgroup b runs tiles b, b + grid, ...; the
+// HBM loads of the next tile's first stage are issued right after the current
+// tile's first stage has consumed its registers, so they are in flight while
+// the current tile runs its LDS stages and stores.
+template <int L, int R0, int NT, bool SPLIT>
+__device__ __forceinline__ void row_pipe(const KParams& kp, uint32_t* lds) {
+  using G = RowGeom<L, R0, NT>;
+  constexpr int P1 = pow16(G::S - 1);
+  const int64_t ntiles = (kp.ntrans + G::TPB - 1) / G::TPB;
+  const FOps f = load_fops<SPLIT>(kp.fimg);
+  auto valid_of = [&](int64_t w) {
+    const int64_t rem = kp.ntrans - w * G::TPB;
+    return rem < G::TPB ? (int)rem : G::TPB;
+  };
+  int64_t w = blockIdx.x;
+  if (w >= ntiles) return;
+  Row16Regs<G> r;
+  row_stage16_load<G, P1, SPLIT>(kp, valid_of(w), w * G::TPB * L, r);
+  for (; w < ntiles; w += gridDim.x) {
+    const int valid = valid_of(w);
+    const int64_t g0 = w * G::TPB * L;
+    row_stage16<G, P1, true, SPLIT, true>(kp, lds, valid, g0, f, &r);
+    const int64_t wn = w + gridDim.x;
+    if (wn < ntiles) row_stage16_load<G, P1, SPLIT>(kp, valid_of(wn), wn * G::TPB * L, r);
+    __syncthreads();
+    row_stages_from<G, G::S - 2, SPLIT>(kp, lds, valid, g0, f);
+    __syncthreads();  // the next tile's first stage rewrites LDS
+  }
+}
+
 template <int L, int R0, int NT, bool SPLIT>
 __global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
   extern __shared__ uint32_t lds[];
-  row_body<L, R0, NT, SPLIT>(kp, blockIdx.x, lds);
+  if constexpr (RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
+    row_pipe<L, R0, NT, SPLIT>(kp, lds);
+  else
+    row_body<L, R0, NT, SPLIT>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================

@@ -348,6 +348,7 @@ struct DevPass {
   float2* xtw_hi = nullptr;
   int xbits = 0;
   int persist_grid = 0;      // resident workgroups for the grouped (persistent) launch
+  int single_grid = 0;       // resident workgroups of the single kernel (persistent variants)
 };
 
 }  // namespace
@@ -456,6 +457,16 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
         per_cu = 1;
       }
       dpp.persist_grid = per_cu * ncu;
+      if (dpp.fn.persistent) {
+        per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)dpp.fn.single,
+                                                        sp.key.NT, sp.lds) != hipSuccess ||
+            per_cu <= 0) {
+          (void)hipGetLastError();
+          per_cu = 1;
+        }
+        dpp.single_grid = per_cu * ncu;
+      }
       void* t = nullptr;
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
@@ -582,6 +593,8 @@ tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s
       if (i == np - 1) dpp.spec.dst = 1;
       int64_t grid = 0;
       KParams kp = make_kparams(p, dpp, cin, cout, nb, p->ws, &grid);
+      // persistent variants: one resident wave of workgroups strides over the tiles
+      if (dpp.fn.persistent && dpp.single_grid > 0) grid = std::min<int64_t>(grid, dpp.single_grid);
       void* args[] = {&kp};
       if (hipLaunchKernel((const void*)dpp.fn.single, dim3((unsigned)grid),
                           dim3(dpp.spec.key.NT), args, dpp.spec.lds, s) != hipSuccess) {
