@@ -50,8 +50,22 @@ __device__ __forceinline__ void lds_st4(uint32_t* lds, int p, u4 v) {
 __device__ __forceinline__ uint32_t lds_ld1(const uint32_t* lds, int p) { return lds[lds_addr(p)]; }
 __device__ __forceinline__ void lds_st1(uint32_t* lds, int p, uint32_t v) { lds[lds_addr(p)] = v; }
 
-__device__ __forceinline__ u4 gld4(const uint32_t* ptr) { return *reinterpret_cast<const u4*>(ptr); }
-__device__ __forceinline__ void gst4(uint32_t* ptr, u4 v) { *reinterpret_cast<u4*>(ptr) = v; }
+// Global-memory accesses through address-space-1 pointers: grouped launches
+// read their buffer and table pointers from a descriptor in memory, where the
+// compiler cannot infer the address space and would otherwise emit flat
+// accesses (64-bit VGPR addresses, and LDS-counter waits at every barrier).
+#define TCFFT_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ u4 gld4(const uint32_t* ptr) {
+  return *(const TCFFT_GLOBAL u4*)(ptr);
+}
+__device__ __forceinline__ void gst4(uint32_t* ptr, u4 v) { *(TCFFT_GLOBAL u4*)(ptr) = v; }
+__device__ __forceinline__ void gst1(uint32_t* ptr, uint32_t v) {
+  *(TCFFT_GLOBAL uint32_t*)(ptr) = v;
+}
+// Table lookup: element i of a read-only FP32 complex table.
+__device__ __forceinline__ float2 tld(const float2* tab, int64_t i) {
+  return *(const TCFFT_GLOBAL float2*)(tab + i);
+}
 
 // Position of the digit-reversed "high" index of the last stage: natural low
 // output index klow = k0 + R0*(k1 + 16 k2 + ... + 16^(S-2) k_{S-1}) sits at
@@ -75,7 +89,7 @@ struct FOps {
 };
 template <bool SPLIT>
 __device__ __forceinline__ FOps load_fops(const void* fimg) {
-  const h8* f = reinterpret_cast<const h8*>(fimg);
+  const TCFFT_GLOBAL h8* f = (const TCFFT_GLOBAL h8*)(fimg);
   const int lane = threadIdx.x & 63;
   FOps o;
   o.rh = f[lane];
@@ -160,7 +174,7 @@ __device__ __forceinline__ TwB load_twb(const float2* tw, int g, int mul) {
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int t = 1; t < 4; ++t) B.b[j][t - 1] = tw[(4 * g + j) * t * mul];
+    for (int t = 1; t < 4; ++t) B.b[j][t - 1] = tld(tw, (4 * g + j) * t * mul);
   return B;
 }
 
@@ -175,7 +189,7 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
 #pragma unroll
   for (int k = 1; k < R0; ++k)
 #pragma unroll
-    for (int t = 1; t < 4; ++t) bt[k][t] = kp.tw[k * t];
+    for (int t = 1; t < 4; ++t) bt[k][t] = tld(kp.tw, k * t);
   constexpr int ITER = (G::NCQ0 + G::NT - 1) / G::NT;
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
@@ -197,7 +211,7 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
     float2 a[R0];
 #pragma unroll
     for (int k = 1; k < R0; ++k) {
-      a[k] = kp.tw[k * lo0];  // W_L^{k lo0}, k lo0 < L
+      a[k] = tld(kp.tw, k * lo0);  // W_L^{k lo0}, k lo0 < L
       a[k].x *= kp.r0scale;
       a[k].y *= kp.r0scale;
     }
@@ -328,7 +342,7 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
     if constexpr (P > 1) {
       const int r0 = col0 % P;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = kp.tw[(4 * g + j) * r0 * TM];
+      for (int j = 0; j < 4; ++j) a[j] = tld(kp.tw, (4 * g + j) * r0 * TM);
     }
     uint32_t oh[4][4], ol[4][4];  // [t][j]
 #pragma unroll
@@ -386,8 +400,8 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int64_t o = g0 + (int64_t)tau * L + col % (L / 16) + (L / 16) * (4 * g + j);
-              kp.out[o] = oh[t][j];
-              if constexpr (SPLIT) kp.out[kp.out_plane + o] = ol[t][j];
+              gst1(kp.out + o, oh[t][j]);
+              if constexpr (SPLIT) gst1(kp.out + kp.out_plane + o, ol[t][j]);
             }
           }
         }
@@ -432,11 +446,11 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
   for (int k = 1; k < R0; ++k)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float2 w = kp.tw[k * (4 * g + i) * P];
+      float2 w = tld(kp.tw, k * (4 * g + i) * P);
       w.x *= kp.r0scale;
       w.y *= kp.r0scale;
       wm[k][i] = w;
-      bt[k][i] = kp.tw[k * i];
+      bt[k][i] = tld(kp.tw, k * i);
     }
   const TwB B = load_twb(kp.tw, g, R0);  // W_{16P}^{(4g+j) t} = W_L^{(4g+j) t R0}
 #pragma unroll
@@ -458,14 +472,14 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
     float2 at[R0][4];  // W_L^{k (lo0 + t)}
 #pragma unroll
     for (int k = 1; k < R0; ++k) {
-      const float2 a = kp.tw[k * lo0];
+      const float2 a = tld(kp.tw, k * lo0);
       at[k][0] = a;
 #pragma unroll
       for (int t = 1; t < 4; ++t) at[k][t] = cmul(a, bt[k][t]);
     }
     float2 a16[4];  // W_{16P}^{(4g+j) lo0}
 #pragma unroll
-    for (int j = 0; j < 4; ++j) a16[j] = kp.tw[(4 * g + j) * lo0 * R0];
+    for (int j = 0; j < 4; ++j) a16[j] = tld(kp.tw, (4 * g + j) * lo0 * R0);
     uint32_t oh[R0][4][4], ol[R0][4][4];  // [k][t][j]
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -651,7 +665,7 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
     }
     float2 wt[R0];
 #pragma unroll
-    for (int k = 0; k < R0; ++k) wt[k] = kp.tw[k * lo];
+    for (int k = 0; k < R0; ++k) wt[k] = tld(kp.tw, k * lo);
     float2 v[4][R0];
 #pragma unroll
     for (int d = 0; d < R0; ++d)
@@ -684,8 +698,8 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
 // of two below 2^32, so the exponent needs only the low 32 bits of ci * k.
 __device__ __forceinline__ float2 xtwiddle(const KParams& kp, uint32_t ci, uint32_t k) {
   const uint32_t e = (ci * k) & kp.xmask;
-  const float2 a = kp.xtw_lo[e & ((1u << kp.xbits) - 1u)];
-  const float2 b = kp.xtw_hi[e >> kp.xbits];
+  const float2 a = tld(kp.xtw_lo, e & ((1u << kp.xbits) - 1u));
+  const float2 b = tld(kp.xtw_hi, e >> kp.xbits);
   return cmul(a, b);
 }
 
@@ -734,7 +748,7 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if constexpr (P > 1) {
-        const float2 v = kp.tw[(4 * g + j) * lo * (L / (16 * P))];  // W_{16P}^{row lo}
+        const float2 v = tld(kp.tw, (4 * g + j) * lo * (L / (16 * P)));  // W_{16P}^{row lo}
 #pragma unroll
         for (int t = 0; t < 4; ++t) w[t][j] = v;
       } else if constexpr (XTW) {
@@ -743,7 +757,7 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
         if (kp.xdiv == 1) {
           // W_M^{(ci + t) k} = W_M^{ci k} * (W_M^k)^t
           const float2 a = xtwiddle(kp, ci, k);
-          const float2 b1 = kp.xtw_lo[k];  // W_M^k (k < L <= 2^xbits)
+          const float2 b1 = tld(kp.xtw_lo, k);  // W_M^k (k < L <= 2^xbits)
           w[0][j] = a;
 #pragma unroll
           for (int t = 1; t < 4; ++t) w[t][j] = cmul(w[t - 1][j], b1);
@@ -856,7 +870,7 @@ __device__ __forceinline__ void col_stage_fused(const KParams& kp, uint32_t* lds
   for (int k = 1; k < R0; ++k)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float2 w = kp.tw[k * (4 * g + i) * P];
+      float2 w = tld(kp.tw, k * (4 * g + i) * P);
       w.x *= kp.r0scale;
       w.y *= kp.r0scale;
       wm[k][i] = w;
@@ -881,13 +895,13 @@ __device__ __forceinline__ void col_stage_fused(const KParams& kp, uint32_t* lds
     float2 w[R0][4];
 #pragma unroll
     for (int k = 1; k < R0; ++k) {
-      const float2 a = kp.tw[k * lo];
+      const float2 a = tld(kp.tw, k * lo);
 #pragma unroll
       for (int i = 0; i < 4; ++i) w[k][i] = cmul(wm[k][i], a);
     }
     float2 a16[4];  // W_{16P}^{(4g+j) lo}
 #pragma unroll
-    for (int j = 0; j < 4; ++j) a16[j] = kp.tw[(4 * g + j) * lo * R0];
+    for (int j = 0; j < 4; ++j) a16[j] = tld(kp.tw, (4 * g + j) * lo * R0);
     uint32_t oh[R0][4][4], ol[R0][4][4];  // [k][t][j]
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -990,7 +1004,16 @@ __global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
 // rewriting device memory.  The grid is persistent: each workgroup strides
 // over the job tiles.
 // ===========================================================================
-__device__ __forceinline__ int find_job(const int64_t* __restrict__ prefix, int njobs, int64_t w) {
+// The group header, descriptor table and prefix array are written by the host
+// before the launch and only read by it: read through the constant address
+// space, they load into scalar registers (uniform per workgroup) instead of
+// taking ~40 vector registers per lane for the descriptor.
+#define TCFFT_CONST __attribute__((address_space(4)))
+typedef const TCFFT_CONST GroupHdr CGroupHdr;
+typedef const TCFFT_CONST KParams CKParams;
+typedef const TCFFT_CONST int64_t CInt64;
+
+__device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
   int lo = 0, hi = njobs - 1;  // largest j with prefix[j] <= w
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1000,12 +1023,16 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ prefix, int 
   return lo;
 }
 
+// FP16 row tiles use 64 KB of LDS, so two workgroups share a CU: the register
+// budget is capped to match (the persistent loop otherwise keeps enough
+// loop-invariant addresses live to drop to one workgroup per CU).
 template <int L, int R0, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
-  const KParams* __restrict__ jobs = hdr->jobs;
-  const int64_t* __restrict__ prefix = hdr->prefix;
-  const int njobs = (int)hdr->njobs;
+  CGroupHdr* h = (CGroupHdr*)hdr;
+  CKParams* jobs = (CKParams*)h->jobs;
+  CInt64* prefix = (CInt64*)h->prefix;
+  const int njobs = (int)h->njobs;
   const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
@@ -1018,9 +1045,10 @@ __global__ __launch_bounds__(NT) void row_kernel_multi(const GroupHdr* __restric
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
 __global__ __launch_bounds__(NT) void col_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
-  const KParams* __restrict__ jobs = hdr->jobs;
-  const int64_t* __restrict__ prefix = hdr->prefix;
-  const int njobs = (int)hdr->njobs;
+  CGroupHdr* h = (CGroupHdr*)hdr;
+  CKParams* jobs = (CKParams*)h->jobs;
+  CInt64* prefix = (CInt64*)h->prefix;
+  const int njobs = (int)h->njobs;
   const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
