@@ -38,6 +38,8 @@ bool find_col_kernels_256(const KernelKey& k, KernelFns* out) {
   COLK(512, 2, 32, 256)
   COLK(512, 2, 64, 256)
   COLK(512, 2, 16, 256)
+  COLK(512, 2, 8, 256)
+  COLK(256, 1, 8, 128)
   return false;
 }
 

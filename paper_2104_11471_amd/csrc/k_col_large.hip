@@ -34,6 +34,7 @@ namespace tcfft {
 bool find_col_kernels_large(const KernelKey& k, KernelFns* out) {
   COLK(1024, 4, 32, 256)
   COLK(1024, 4, 16, 256)
+  COLK(1024, 4, 8, 256)
   COLK(2048, 8, 16, 256)
   COLK(2048, 8, 8, 256)
   return false;

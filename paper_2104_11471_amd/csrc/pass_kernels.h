@@ -63,8 +63,10 @@ __device__ __forceinline__ void gst1(uint32_t* ptr, uint32_t v) {
   *(TCFFT_GLOBAL uint32_t*)(ptr) = v;
 }
 // Table lookup: element i of a read-only FP32 complex table.
+typedef float f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 tld(const float2* tab, int64_t i) {
-  return *(const TCFFT_GLOBAL float2*)(tab + i);
+  const f2v v = *(const TCFFT_GLOBAL f2v*)(tab + i);
+  return make_float2(v.x, v.y);
 }
 
 // Position of the digit-reversed "high" index of the last stage: natural low
@@ -1013,6 +1015,17 @@ typedef const TCFFT_CONST GroupHdr CGroupHdr;
 typedef const TCFFT_CONST KParams CKParams;
 typedef const TCFFT_CONST int64_t CInt64;
 
+// Copy of descriptor j (word by word: the struct has no constructor from the
+// constant address space).
+__device__ __forceinline__ KParams load_job(CKParams* jobs, int j) {
+  KParams kp;
+  const TCFFT_CONST uint32_t* src = (const TCFFT_CONST uint32_t*)(jobs + j);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&kp);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(KParams) / 4); ++i) dst[i] = src[i];
+  return kp;
+}
+
 __device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
   int lo = 0, hi = njobs - 1;  // largest j with prefix[j] <= w
   while (lo < hi) {
@@ -1036,7 +1049,7 @@ __global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const Grou
   const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
-    const KParams kp = jobs[j];
+    const KParams kp = load_job(jobs, j);
     row_body<L, R0, NT, SPLIT>(kp, w - prefix[j], lds);
     __syncthreads();  // the next tile's first stage rewrites LDS
   }
@@ -1052,7 +1065,7 @@ __global__ __launch_bounds__(NT) void col_kernel_multi(const GroupHdr* __restric
   const int64_t total = njobs > 0 ? prefix[njobs] : 0;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
-    const KParams kp = jobs[j];
+    const KParams kp = load_job(jobs, j);
     col_body<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, w - prefix[j], lds);
     __syncthreads();
   }

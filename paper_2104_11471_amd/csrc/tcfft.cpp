@@ -883,7 +883,7 @@ std::vector<Choice> candidates_base(const Desc& d) {
   const bool longp = d.rank == 1 && d.nx > kMaxRowL;
   if (!longp) {
     for (int nt : {256, 512})
-      for (int cmax : {64, 32, 16}) {
+      for (int cmax : {64, 32, 16, 8}) {
         if (d.rank == 1 && cmax != 64) continue;
         Choice c;
         c.row_nt = nt;
@@ -896,7 +896,7 @@ std::vector<Choice> candidates_base(const Desc& d) {
   for (int e1 = 4; e1 <= 11; ++e1) {  // two passes
     const int e2 = lg - e1;
     if (e2 < 4 || e2 > 11) continue;
-    for (int cmax : {64, 32, 16}) {
+    for (int cmax : {64, 32, 16, 8}) {
       Choice c;
       c.cmax = cmax;
       c.nf = 2;

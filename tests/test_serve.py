@@ -32,16 +32,53 @@ def test_stream_results_equal_alone(graphs, window):
     assert summary["requests"] == len(reqs)
     assert st["max_inflight_bytes"] <= 8 << 30
     byid = {r.rid: r for r in reqs}
+    # each checked request again, alone on the idle server (same plans, no
+    # other request in its batch): bitwise the result it got in the mix
     for tag, got in keep.items():
         r = byid[tag]
         k = serve.shape_class(r)
-        p = tcfft.Plan(r.dims, r.batch, precision=k[2])
-        x = serve.PayloadPool.view(pool.inp[k], k, r.batch)
-        alone = p(x)
+        out = torch.empty_like(pool.out[k][0])
+        assert srv.submit(r.rank, r.dims, r.batch, -1, k[2], pool.inp[k].data_ptr(),
+                          out.data_ptr(), tag) == 0
+        srv.wait_idle(20000)
+        done = srv.poll()
+        assert [d[0] for d in done] == [tag] and done[0][1] == 0
         torch.cuda.synchronize()
+        alone = serve.PayloadPool.view(out, k, r.batch)
         got = serve.PayloadPool.view(got, k, r.batch)
         assert torch.equal(got.view(torch.int16), alone.view(torch.int16)), (tag, k)
+        # and it is the DFT: a sampled transform against the oracle
+        x = serve.PayloadPool.view(pool.inp[k], k, r.batch)
+        _check_against_oracle(r, k, x, alone)
     srv.close()
+
+
+def _check_against_oracle(r, k, x, y):
+    import oracle
+    from tests.gpu_util import FP16_TOL, SPLIT_TOL
+    xs = x.cpu().numpy().astype(np.float64)
+    ys = y.cpu().numpy().astype(np.float64)
+    if k[2] == "split":
+        xc = (xs[0, 0, ..., 0] + 2.0 ** -11 * xs[1, 0, ..., 0]) + 1j * (xs[0, 0, ..., 1] + 2.0 ** -11 * xs[1, 0, ..., 1])
+        yc = (ys[0, 0, ..., 0] + 2.0 ** -11 * ys[1, 0, ..., 0]) + 1j * (ys[0, 0, ..., 1] + 2.0 ** -11 * ys[1, 0, ..., 1])
+        tol = SPLIT_TOL
+    else:
+        xc = xs[0, ..., 0] + 1j * xs[0, ..., 1]
+        yc = ys[0, ..., 0] + 1j * ys[0, ..., 1]
+        tol = FP16_TOL
+    ref = oracle.fft(xc, -1) if r.rank == 1 else oracle.fft2(xc, -1)
+    d = tcfft_scale(r, k)
+    err = np.linalg.norm(yc * 2.0 ** d - ref) / np.linalg.norm(ref)
+    assert err <= tol, (r.dims, r.batch, k, err)
+
+
+def tcfft_scale(r, k):
+    """Scale of the server's plan for this shape: the server tunes its
+    multi-pass 1D single-transform plans, and the same key hits the same
+    cached choice."""
+    from paper_2104_11471_amd import tcfft
+    flags = tcfft.FLAG_TUNE if (r.rank == 1 and r.dims[0] > 16384) else 0
+    return tcfft.Plan(r.dims, 1, precision=k[2], flags=flags).scale_log2
 
 
 @pytest.mark.gpu
