@@ -4,7 +4,7 @@
 namespace tcfft {
 
 #define ROWK(L_, R_, N_)                                                             \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_) {                    \
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore) {      \
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true>;                          \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true>;                      \
@@ -14,6 +14,20 @@ namespace tcfft {
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, false>;                     \
       out->persistent = RowPipe<RowGeom<L_, R_, N_>, false>::value;                  \
     }                                                                                \
+    return true;                                                                     \
+  }
+
+// Transposed-store variants (second pass of a four-step transform).
+#define ROWKT(L_, R_, N_)                                                            \
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && k.tstore) {       \
+    if (k.split) {                                                                   \
+      out->single = (KernelFn)row_kernel<L_, R_, N_, true, true>;                    \
+      out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true, true>;                \
+    } else {                                                                        \
+      out->single = (KernelFn)row_kernel<L_, R_, N_, false, true>;                   \
+      out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, false, true>;               \
+    }                                                                                \
+    out->persistent = false;                                                         \
     return true;                                                                     \
   }
 
@@ -47,6 +61,9 @@ bool find_row_kernels(const KernelKey& k, KernelFns* out) {
   ROWK(16384, 4, 256)
   ROWK(8192, 2, 512)
   ROWK(16384, 4, 512)
+  ROWKT(256, 1, 256)
+  ROWKT(512, 2, 256)
+  ROWKT(1024, 4, 256)
   return false;
 }
 

@@ -39,7 +39,7 @@ static_assert(sizeof(KParams) == 168, "KParams layout changed: host and device m
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
-enum KernelKind { K_ROW = 0, K_COL = 1 };
+enum KernelKind { K_ROW = 0, K_COL = 1, K_BIG = 2 };
 
 struct KernelKey {
   int kind;    // KernelKind
@@ -77,6 +77,7 @@ bool find_row_kernels(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_small(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_256(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_large(const KernelKey& key, KernelFns* out);
+bool find_big_kernels(const KernelKey& key, KernelFns* out);
 // Returns the single-launch kernel for `key`, or nullptr.
 KernelFn find_kernel(const KernelKey& key);
 // Dynamic LDS bytes the kernel needs.

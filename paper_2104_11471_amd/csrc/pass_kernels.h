@@ -280,7 +280,12 @@ __device__ __forceinline__ void row_stage16_load(const KParams& kp, int valid, i
   }
 }
 
-template <class G, int P, bool SRCG, bool SPLIT, bool PRE = false>
+// TT (last stage only): transposed store for the second pass of a four-step
+// transform.  The 4 tiles of a lane are 4 consecutive lines at one output
+// index, so the lane writes output k of lines tau0..tau0+3 as one 16-byte
+// group at b (q L) + k s_out + (line mod q) (line = global line index, q lines
+// per transform): the pass writes X[k1 + q k2] with no gather.
+template <class G, int P, bool SRCG, bool SPLIT, bool PRE = false, bool TT = false>
 __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, int valid,
                                             int64_t g0, const FOps& f,
                                             const Row16Regs<G>* pre = nullptr) {
@@ -295,6 +300,9 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
   for (int qq = 0; qq < G::QPW; ++qq) {
     const int Q = wave * G::QPW + qq;
     const int col0 = 4 * c16 + 64 * Q;
+    static_assert(!TT || (P == 1 && !SRCG && G::TPB >= 4 && G::TPB % 4 == 0), "transposed store");
+    const int tau0 = TT ? 4 * ((col0 >> 2) % (G::TPB / 4)) : 0;
+    const int klowT = TT ? (col0 >> 2) / (G::TPB / 4) : 0;
     u4 xh[4], xl[4];  // xh[t] = rows 4g..4g+3 of tile t
     if constexpr (P > 1) {
       // tiles along the contiguous low index: one 16-byte access per row
@@ -324,12 +332,13 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
         }
     } else {
       // last stage: rows are contiguous; columns enumerate natural order
+      // (transposed store: lines tau0 + t at output column klowT)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int col = col0 + t;
-        int tau = col / (L / 16);
+        int tau = TT ? tau0 + t : col / (L / 16);
         if constexpr (SRCG && G::TPB > 1) tau = tau < valid ? tau : 0;
-        const int p = tau * L + posrev_hi<R0, S>(col % (L / 16)) * 16 + 4 * g;
+        const int p = tau * L + posrev_hi<R0, S>(TT ? klowT : col % (L / 16)) * 16 + 4 * g;
         if constexpr (SRCG) {
           xh[t] = gld4(kp.in + g0 + p);
           if constexpr (SPLIT) xl[t] = gld4(kp.in + kp.in_plane + g0 + p);
@@ -370,7 +379,27 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
       }
     } else {
       // natural output index of (row, col): tau*L + klow + (L/16)*row
-      if constexpr (L / 16 >= 4) {
+      if constexpr (TT) {
+        const int64_t line0 = g0 / L + tau0;
+        const int64_t b = line0 >> kp.q_log2;
+        const int64_t base = b * kp.q * L + (line0 & (kp.q - 1));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t o = base + (int64_t)(klowT + (L / 16) * (4 * g + j)) * kp.s_out;
+          if (tau0 + 3 < valid) {
+            gst4(kp.out + o, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+            if constexpr (SPLIT)
+              gst4(kp.out + kp.out_plane + o, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (tau0 + t < valid) {
+                gst1(kp.out + o + t, oh[t][j]);
+                if constexpr (SPLIT) gst1(kp.out + kp.out_plane + o + t, ol[t][j]);
+              }
+          }
+        }
+      } else if constexpr (L / 16 >= 4) {
         const int tau = col0 / (L / 16);
         if (G::TPB == 1 || tau < valid) {
           const int klow0 = col0 % (L / 16);
@@ -530,19 +559,19 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
   }
 }
 
-template <class G, int E, bool SPLIT>
+template <class G, int E, bool SPLIT, bool TT = false>
 __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds, int valid,
                                                 int64_t g0, const FOps& f) {
   // radix-16 stages with stride 16^E, 16^(E-1), ..., 1, all reading LDS
-  row_stage16<G, pow16(E), false, SPLIT>(kp, lds, valid, g0, f);
+  row_stage16<G, pow16(E), false, SPLIT, false, E == 0 && TT>(kp, lds, valid, g0, f);
   if constexpr (E > 0) {
     __syncthreads();
-    row_stages_from<G, E - 1, SPLIT>(kp, lds, valid, g0, f);
+    row_stages_from<G, E - 1, SPLIT, TT>(kp, lds, valid, g0, f);
   }
 }
 
 // One workgroup's share of a row pass: workgroup index wg of the pass.
-template <int L, int R0, int NT, bool SPLIT>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false>
 __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = RowGeom<L, R0, NT>;
   const int64_t t0 = wg * G::TPB;
@@ -553,16 +582,16 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
   if constexpr (RowFused<G>::value) {
     row_stage_fused<G, SPLIT>(kp, lds, valid, g0, f);
     __syncthreads();
-    row_stages_from<G, G::S - 2, SPLIT>(kp, lds, valid, g0, f);
+    row_stages_from<G, G::S - 2, SPLIT, TT>(kp, lds, valid, g0, f);
   } else if constexpr (R0 > 1) {
     row_stage_r0<G, SPLIT>(kp, lds, valid, g0);
     __syncthreads();
-    row_stages_from<G, G::S - 1, SPLIT>(kp, lds, valid, g0, f);
+    row_stages_from<G, G::S - 1, SPLIT, TT>(kp, lds, valid, g0, f);
   } else {
     row_stage16<G, pow16(G::S - 1), true, SPLIT>(kp, lds, valid, g0, f);
     if constexpr (G::S > 1) {
       __syncthreads();
-      row_stages_from<G, G::S - 2, SPLIT>(kp, lds, valid, g0, f);
+      row_stages_from<G, G::S - 2, SPLIT, TT>(kp, lds, valid, g0, f);
     }
   }
 }
@@ -610,13 +639,13 @@ __device__ __forceinline__ void row_pipe(const KParams& kp, uint32_t* lds) {
   }
 }
 
-template <int L, int R0, int NT, bool SPLIT>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false>
 __global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
   extern __shared__ uint32_t lds[];
-  if constexpr (RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
+  if constexpr (!TT && RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
     row_pipe<L, R0, NT, SPLIT>(kp, lds);
   else
-    row_body<L, R0, NT, SPLIT>(kp, blockIdx.x, lds);
+    row_body<L, R0, NT, SPLIT, TT>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -1039,7 +1068,7 @@ __device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
 // FP16 row tiles use 64 KB of LDS, so two workgroups share a CU: the register
 // budget is capped to match (the persistent loop otherwise keeps enough
 // loop-invariant addresses live to drop to one workgroup per CU).
-template <int L, int R0, int NT, bool SPLIT>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false>
 __global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
   CGroupHdr* h = (CGroupHdr*)hdr;
@@ -1050,7 +1079,7 @@ __global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const Grou
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
     const KParams kp = load_job(jobs, j);
-    row_body<L, R0, NT, SPLIT>(kp, w - prefix[j], lds);
+    row_body<L, R0, NT, SPLIT, TT>(kp, w - prefix[j], lds);
     __syncthreads();  // the next tile's first stage rewrites LDS
   }
 }

@@ -5,7 +5,8 @@ namespace tcfft {
 
 bool find_kernels(const KernelKey& k, KernelFns* out) {
   return find_row_kernels(k, out) || find_col_kernels_small(k, out) ||
-         find_col_kernels_256(k, out) || find_col_kernels_large(k, out);
+         find_col_kernels_256(k, out) || find_col_kernels_large(k, out) ||
+         find_big_kernels(k, out);
 }
 
 KernelFn find_kernel(const KernelKey& k) {
@@ -14,12 +15,14 @@ KernelFn find_kernel(const KernelKey& k) {
 }
 
 size_t kernel_lds_bytes(const KernelKey& k) {
+  if (k.kind == K_BIG) return 16384 * 4;  // 4 sub-transforms of 4096 at a time
   const int64_t pts = kernel_points_per_wg(k);
   return (size_t)pts * 4 * (k.split ? 2 : 1);
 }
 
 int64_t kernel_points_per_wg(const KernelKey& k) {
   if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
+  if (k.kind == K_BIG) return k.L;
   return (int64_t)k.L * k.C;
 }
 

@@ -81,6 +81,8 @@ struct Choice {
   int f[3] = {0, 0, 0};
   int chunk = 0;     // multi-pass plans: transforms per chunk (0 = whole batch); all passes
                      // of a chunk run before the next chunk, reusing one workspace region
+  int p2row = 0;     // two-pass 1D: pass 1 stores in natural order and pass 2 is a row
+                     // pass over contiguous lines with a transposed store
 };
 
 struct PlanSpec {
@@ -121,11 +123,19 @@ tcfft_status row_choice(int L, int nt, bool split, KernelKey* out) {
   return TCFFT_ERR_UNSUPPORTED;
 }
 
-// Row pass over `lines` contiguous lines of L points.
-tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst) {
+// Row pass over `lines` contiguous lines of L points.  q > 0: transposed store
+// of lines in groups of q (line l of group b, output k at b q L + k q + l).
+tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst, int64_t q = 0) {
   PassSpec p;
   tcfft_status st = row_choice(L, ps.ch.row_nt, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key);
   if (st) return st;
+  if (q > 0) {
+    p.key.tstore = 1;
+    p.key.NT = 256;
+    if (!find_kernel(p.key) || q % 4 != 0 || !is_pow2(q)) return TCFFT_ERR_UNSUPPORTED;
+    p.q = q;
+    p.s_out = q;
+  }
   const int64_t tpb = kernel_points_per_wg(p.key) / L;
   p.tpb = tpb;
   p.ntrans = lines;
@@ -135,6 +145,23 @@ tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst) 
   p.src = src;
   p.dst = dst;
   p.scale = pass_scale(L);
+  ps.passes.push_back(p);
+  return TCFFT_OK;
+}
+
+// Single-pass 65536-point transform (one workgroup per line, FP16 only).
+tcfft_status add_big_pass(PlanSpec& ps, int64_t lines) {
+  PassSpec p;
+  p.key = KernelKey{K_BIG, 65536, 1, 0, 512, 0, 0, 0};
+  if (!find_kernel(p.key)) return TCFFT_ERR_UNSUPPORTED;
+  p.tpb = 1;
+  p.ntrans = lines;
+  p.lines_per_batch = lines / ps.d.batch;
+  p.grid = lines;
+  p.lds = kernel_lds_bytes(p.key);
+  p.src = 0;
+  p.dst = 1;
+  p.scale = pass_scale(65536);
   ps.passes.push_back(p);
   return TCFFT_OK;
 }
@@ -229,6 +256,10 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     const int64_t N = d.nx;
     if (N <= kMaxRowL) {
       st = add_row_pass(ps, (int)N, B, 0, 1);
+    } else if (ch.nf == 1) {
+      // the single-pass kernel (65536 points, FP16)
+      if (N != 65536 || ch.f[0] != 65536 || d.prec != TCFFT_PREC_FP16) return TCFFT_ERR_UNSUPPORTED;
+      st = add_big_pass(ps, B);
     } else {
       std::vector<int> f = long_split(N);
       if (ch.nf > 0) {
@@ -240,7 +271,13 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
         }
         if (prod != N) return TCFFT_ERR_UNSUPPORTED;
       }
-      if (f.size() == 2) {
+      if (f.size() == 2 && ch.p2row) {
+        const int64_t N1 = f[0], N2 = f[1];
+        // pass 1: N1-point DFTs over n1 (stride N2), twiddle W_N^{n2 k1}, natural
+        // store Z[k1][n2]; pass 2: rows of N2 contiguous points, X[k1 + N1 k2]
+        st = add_col_pass(ps, (int)N1, N2, B, N, N, N2, N2, 0, false, N, 1, 0, 2);
+        if (!st) st = add_row_pass(ps, (int)N2, B * N1, 2, 1, N1);
+      } else if (f.size() == 2) {
         const int64_t N1 = f[0], N2 = f[1];
         // pass 1: N1-point DFTs over n1 (stride N2), twiddle W_N^{n2 k1},
         // transposed store Z[n2][k1]
@@ -290,13 +327,14 @@ std::string describe(const PlanSpec& ps) {
   std::snprintf(b, sizeof b,
                 "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,"
-                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d},\"tuned\":%s,"
+                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
                 "\"tuned_us\":%.2f,\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
                 ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
                 precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes, ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
-                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.tuned ? "true" : "false", ps.tuned_us);
+                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
+                ps.tuned_us);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
@@ -320,7 +358,8 @@ std::string describe(const PlanSpec& ps) {
                   "%s{\"kernel\":\"%s\",\"L\":%d,\"radices\":%s,\"C\":%d,\"NT\":%d,\"grid\":%lld,"
                   "\"lds\":%zu,\"xtw\":%d,\"tstore\":%d,\"scale\":%d,\"src\":%d,\"dst\":%d,"
                   "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld}",
-                  i ? "," : "", p.key.kind == K_ROW ? "row" : "col", p.key.L, rad.c_str(), p.key.C,
+                  i ? "," : "", p.key.kind == K_ROW ? "row" : (p.key.kind == K_BIG ? "big" : "col"),
+                  p.key.L, rad.c_str(), p.key.C,
                   p.key.NT, (long long)p.grid, p.lds, p.key.xtw, p.key.tstore, p.scale, p.src,
                   p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod);
     s += b;
@@ -471,6 +510,11 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
       launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
+      if (sp.key.kind == K_BIG) {  // W_4096 for the 4096-point sub-transforms
+        if ((st = dev_alloc(p, 4096 * sizeof(float2), &t))) break;
+        dpp.xtw_hi = (float2*)t;
+        launch_gen_twiddles(dpp.xtw_hi, 4096, 4096, 1, sgn, s);
+      }
       if (sp.xmod > 0) {
         const int lg = ilog2(sp.xmod);
         // the lo table also serves W_M^k for every output index k < L
@@ -515,7 +559,7 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.out = buf(sp.dst);
   kp.in_plane = split ? plane : 0;
   kp.out_plane = split ? plane : 0;
-  if (sp.key.kind == K_ROW) {
+  if (sp.key.kind != K_COL) {
     kp.ntrans = sp.lines_per_batch * batch;
     *grid = (kp.ntrans + sp.tpb - 1) / sp.tpb;
   } else {
@@ -870,6 +914,7 @@ std::vector<Choice> candidates(const Desc& d) {
     const int64_t c = std::max<int64_t>(1, (mb << 20) / per);
     if (c >= d.batch) continue;
     for (Choice ch : base) {
+      if (ch.nf == 1) continue;  // single pass: nothing to chunk
       ch.chunk = (int)c;
       out.push_back(ch);
     }
@@ -893,16 +938,26 @@ std::vector<Choice> candidates_base(const Desc& d) {
     return out;
   }
   const int lg = ilog2(d.nx);
+  if (d.nx == 65536 && d.prec == TCFFT_PREC_FP16) {  // the single-pass kernel
+    Choice c;
+    c.nf = 1;
+    c.f[0] = 65536;
+    out.push_back(c);
+  }
   for (int e1 = 4; e1 <= 11; ++e1) {  // two passes
     const int e2 = lg - e1;
     if (e2 < 4 || e2 > 11) continue;
-    for (int cmax : {64, 32, 16, 8}) {
-      Choice c;
-      c.cmax = cmax;
-      c.nf = 2;
-      c.f[0] = 1 << e1;
-      c.f[1] = 1 << e2;
-      out.push_back(c);
+    for (int p2row : {0, 1}) {
+      if (p2row && (e2 < 8 || e2 > 10)) continue;  // transposed-store row variants
+      for (int cmax : {64, 32, 16, 8}) {
+        Choice c;
+        c.cmax = cmax;
+        c.nf = 2;
+        c.f[0] = 1 << e1;
+        c.f[1] = 1 << e2;
+        c.p2row = p2row;
+        out.push_back(c);
+      }
     }
   }
   if (lg > 22) {  // three passes
@@ -1174,11 +1229,11 @@ tcfft_status tcfft_tune_cache_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return TCFFT_ERR_INVALID_ARG;
-  std::fprintf(f, "tcfft-tune 2\n");
+  std::fprintf(f, "tcfft-tune 3\n");
   for (const auto& kv : g_tune) {
     const Choice& c = kv.second.first;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf,
-                 c.f[0], c.f[1], c.f[2], c.chunk, kv.second.second);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf,
+                 c.f[0], c.f[1], c.f[2], c.chunk, c.p2row, kv.second.second);
   }
   std::fclose(f);
   return TCFFT_OK;
@@ -1190,15 +1245,15 @@ tcfft_status tcfft_tune_cache_load(const char* path) {
   if (!f) return TCFFT_ERR_INVALID_ARG;
   char key[160];
   int ver = 0;
-  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 2) {
+  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 3) {
     std::fclose(f);
     return TCFFT_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   Choice c;
   double us = 0;
-  while (std::fscanf(f, "%159s %d %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf,
-                     &c.f[0], &c.f[1], &c.f[2], &c.chunk, &us) == 9) {
+  while (std::fscanf(f, "%159s %d %d %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf,
+                     &c.f[0], &c.f[1], &c.f[2], &c.chunk, &c.p2row, &us) == 10) {
     if (c.nf < 0 || c.nf > 3) continue;
     g_tune[key] = {c, us};
   }

@@ -162,7 +162,7 @@ def test_tune_cache_file_errors(tc, tmp_path):
     tc.tune_cache_clear()
     assert tc.tune_cache_size() == 0
     good = tmp_path / "good.txt"
-    good.write_text("tcfft-tune 2\nr1_4096x1_b8_p0 512 64 0 0 0 0 0 123.000\n")
+    good.write_text("tcfft-tune 3\nr1_4096x1_b8_p0 512 64 0 0 0 0 0 0 123.000\n")
     tc.tune_cache_load(str(good))
     assert tc.tune_cache_size() == 1
     tc.tune_cache_save(str(tmp_path / "out.txt"))

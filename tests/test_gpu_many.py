@@ -108,7 +108,7 @@ def test_chunked_execution_is_bitwise_equal(dims, batch, chunk, tmp_path):
     whole = tcfft.Plan(dims, batch)(x)
     key = f"r{len(dims)}_{dims[0]}x{dims[1] if len(dims) == 2 else 1}_b{int(np.log2(batch))}_p0"
     path = tmp_path / "wisdom.txt"
-    path.write_text(f"tcfft-tune 2\n{key} 256 64 0 0 0 0 {chunk} 1.0\n")
+    path.write_text(f"tcfft-tune 3\n{key} 256 64 0 0 0 0 {chunk} 0 1.0\n")
     tcfft.tune_cache_load(str(path))
     p = tcfft.Plan(dims, batch)
     assert p.describe()["choice"]["chunk"] == chunk
