@@ -86,4 +86,23 @@ void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s) {
                      scale);
 }
 
+// Autotuner scratch data: FP16 complex words with re, im in [-1, 1) from a
+// hash of the word index (timing on zeros would run at unrepresentative power).
+__global__ void fill_pattern_kernel(uint32_t* p, int64_t nwords) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nwords) return;
+  uint32_t h = (uint32_t)i * 0x9E3779B1u;
+  h ^= h >> 15;
+  h *= 0x85EBCA77u;
+  h ^= h >> 13;
+  const float re = (float)(h & 0xFFFF) * (1.0f / 32768.0f) - 1.0f;
+  const float im = (float)(h >> 16) * (1.0f / 32768.0f) - 1.0f;
+  p[i] = pack(re, im);
+}
+
+void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s) {
+  hipLaunchKernelGGL(fill_pattern_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s,
+                     (uint32_t*)p, nwords);
+}
+
 }  // namespace tcfft

@@ -96,5 +96,6 @@ void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mul
 // Radix-16 A-operand images, F scaled by `scale` (a power of two):
 // [0] Yr-hi, [1] Yi-hi, [2] Yr-lo, [3] Yi-lo; 64 lanes x 8 halves each.
 void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s);
+void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s);
 
 }  // namespace tcfft
