@@ -229,6 +229,10 @@ def main():
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of the Poisson serving stream (0 = skip)")
+    ap.add_argument("--wisdom", default="",
+                    help="load this autotuner cache before planning (skips re-tuning: a profiled "
+                         "run then uses the plans of an unprofiled one)")
+    ap.add_argument("--save-wisdom", default="", help="save the autotuner cache after planning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -253,6 +257,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": 4 * TOTAL_POINTS, "reps": 3}))
         return
+    if args.wisdom:
+        tcfft.tune_cache_load(args.wisdom)
     plans, xs, xd, yd = {}, {}, {}, {}
     for n in SIZES:
         batch = TOTAL_POINTS // n
@@ -266,6 +272,8 @@ def main():
         d = plans[n].describe()
         log(f"  plan choice={d['choice']} tuned_us={d['tuned_us']:.1f} {d['passes']}")
     torch.cuda.synchronize()
+    if args.save_wisdom:
+        tcfft.tune_cache_save(args.save_wisdom)
 
     def step():
         for n in SIZES:
@@ -302,7 +310,7 @@ def main():
     dom_bytes = 8.0 * TOTAL_POINTS
     dk = plans[dom].describe()["passes"][0]
     kname = (f"row_kernel<{dk['L']}, {dk['radices'][0] if dk['radices'][0] != 16 else 1}, "
-             f"{dk['NT']}, false>")
+             f"{dk['NT']}, false, false>")
     per[dom]["choice"] = plans[dom].describe()["choice"]
     achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
