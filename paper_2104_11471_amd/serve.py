@@ -210,6 +210,7 @@ def run_stream(server: Server, requests, pool: PayloadPool, time_scale: float = 
                 keep[tag] = pool.out[k][oi].clone()
             pool.free[k].append(oi)
             recs[tag]["status"] = st
+            recs[tag]["t_submit"] = ts
             recs[tag]["t_start"] = tb
             recs[tag]["t_done"] = td
             recs[tag]["batch_id"] = bid
@@ -279,7 +280,15 @@ def summarize(recs, wall_s: float) -> dict:
     slow_info = {"n_over_5ms": len(slow),
                  "first_arrival_ms": round(slow[0][0], 2) if slow else None,
                  "last_arrival_ms": round(slow[-1][0], 2) if slow else None}
+    # where the time goes (medians): client submit after the scheduled arrival,
+    # queueing until the batch launch, and launch-to-completion
+    def med(key_a, key_b):
+        v = [(r[key_b] - r[key_a]) / 1e3 for r in ok if r.get(key_a) is not None]
+        return round(float(np.median(v)), 1) if v else None
+    parts = {"submit_after_arrival_us": med("arrival", "t_submit"),
+             "queued_us": med("t_submit", "t_start"), "launch_to_done_us": med("t_start", "t_done")}
     return {"requests": int(lat.size), "failed": int(len(recs) - lat.size), "slow": slow_info,
+            "median_parts": parts,
             "req_per_s": round(lat.size / wall_s, 1), "points_per_s": round(pts / wall_s, 1),
             "gflops": round(flop / wall_s / 1e9, 1), **pct(lat),
             "by_class": {k: pct(v) for k, v in sorted(by_class.items())}}
