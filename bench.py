@@ -54,6 +54,23 @@ def time_launches(fn, reps: int, stream) -> float:
     return start.elapsed_time(end) / 1e3 / reps
 
 
+def time_cold(fn, reps: int, stream, flush) -> float:
+    """Average duration (s) of fn() with the memory-side cache flushed before
+    each call (a 512 MiB buffer rewritten between the timed calls)."""
+    import torch
+    tot = 0.0
+    for _ in range(reps):
+        flush.add_(1)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        fn()
+        end.record(stream)
+        end.synchronize()
+        tot += start.elapsed_time(end) / 1e3
+    return tot / reps
+
+
 def measured_traffic(kernel_name: str):
     """HBM bytes per launch of `kernel_name` from the committed rocprofv3
     counter summary, or None when the kernel source changed since."""
@@ -126,7 +143,9 @@ def cpu_baseline(xs, target_s: float):
 def other_workloads(stream) -> dict:
     """Timing + sampled accuracy of the other workloads: the N=256 x 64 latency
     case, long 1D (2^20 x 16, 2^22 x 4, 2^24 x 1) and batched 2D (256^2 x 1024,
-    512^2 x 256, 1024^2 x 64), FP16 and split.  Not part of `value`."""
+    512^2 x 256, 1024^2 x 64), FP16 and split.  Long 1D is also timed with the
+    memory-side cache flushed before each call (its 64 MiB would otherwise stay
+    resident between calls).  Not part of `value`."""
     import torch
     import oracle
     from paper_2104_11471_amd import inputs, tcfft
@@ -154,6 +173,12 @@ def other_workloads(stream) -> dict:
             p = tcfft.Plan(dims, batch, precision=prec, flags=tcfft.FLAG_TUNE)
             p(xd, yd, stream=stream)
             dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
+            dt_cold = None
+            if kind == "1d":  # 64 MiB of data fits the 256 MB memory-side cache: cold variant too
+                with torch.cuda.stream(stream):
+                    flush = torch.zeros(1 << 27, dtype=torch.int32, device=xd.device)
+                    dt_cold = time_cold(lambda: p(xd, yd, stream=stream), 5, stream, flush)
+                del flush
             npts = int(np.prod(dims)) * batch
             n = int(np.prod(dims))
             row = 0
@@ -169,6 +194,7 @@ def other_workloads(stream) -> dict:
             bpp = 16 if split else 8
             key = f"{kind}_{'x'.join(map(str, dims))}x{batch}_{prec}"
             out[key] = {"us": round(dt * 1e6, 1),
+                        "us_cold_cache": round(dt_cold * 1e6, 1) if dt_cold else None,
                         "gflops": round(5.0 * n * math.log2(n) * batch / dt / 1e9, 1),
                         "gbs_alg": round(bpp * npts / dt / 1e9, 1),
                         "hbm_frac_alg": round(bpp * npts / dt / 1e9 / HBM_PEAK_GBS, 4),
