@@ -1052,8 +1052,18 @@ tcfft_status choose(const Desc& d, Choice* ch, bool* tuned, double* tuned_us) {
     if (a) (void)hipFree(a);
     return TCFFT_ERR_ALLOC;
   }
-  launch_fill_pattern(a, (int64_t)(bytes / 4), nullptr);
-  (void)hipDeviceSynchronize();
+  {  // on a private stream: tuning never waits on other streams' work
+    hipStream_t fs = nullptr;
+    if (hipStreamCreateWithFlags(&fs, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(a);
+      (void)hipFree(b);
+      return TCFFT_ERR_LAUNCH;
+    }
+    launch_fill_pattern(a, (int64_t)(bytes / 4), fs);
+    (void)hipStreamSynchronize(fs);
+    (void)hipStreamDestroy(fs);
+  }
   // round 1: every candidate once; round 2: the 4 fastest again, three times
   // each and interleaved (so clock drift under sustained load hits them
   // alike), keeping each one's best
