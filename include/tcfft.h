@@ -66,7 +66,8 @@ enum {
 enum {
   TCFFT_FLAG_NO_SCALE = 1u, /* S = 0: literally unnormalised (may overflow FP16 for large N) */
   TCFFT_FLAG_NO_GRAPH = 2u, /* reserved: never capture the pass sequence in a HIP graph */
-  TCFFT_FLAG_TUNE = 4u      /* time every planner candidate on the device and keep the fastest */
+  TCFFT_FLAG_TUNE = 4u,     /* time every planner candidate on the device and keep the fastest */
+  TCFFT_FLAG_REAL = 8u      /* real data: FORWARD is real-to-complex, INVERSE complex-to-real */
 };
 
 /*
@@ -80,6 +81,17 @@ enum {
  *   dir        TCFFT_FORWARD or TCFFT_INVERSE
  *   precision  TCFFT_PREC_*
  *   flags      TCFFT_FLAG_* bit set
+ * Real transforms (TCFFT_FLAG_REAL; rank 1, 32 <= N <= 2^27, FP16 or split
+ * precision).  With M = N/2, a real sequence x of N values is stored as M
+ * complex words (word m holds x[2m] in its real half and x[2m+1] in its
+ * imaginary half); the spectrum is the first M+1 bins X[0..M] of the N-point
+ * DFT (the rest follow by Hermitian symmetry), M+1 complex words per
+ * transform.  FORWARD reads batch*M words and writes batch*(M+1); INVERSE
+ * reads batch*(M+1) words (the imaginary parts of X[0] and X[M] are ignored)
+ * and writes batch*M words holding N * x * 2^-S.  The plan runs an M-point
+ * complex transform plus one elementwise pass (Eq. 2 with a radix-2 split of
+ * the real sequence into its even and odd points); split precision stores
+ * both buffers as a hi plane then a lo plane.
  * Allocates the plan's device tables (DFT-matrix operands, twiddles generated
  * in FP64 on the device) and its workspace on the current device; the tables
  * are generated on a private stream that the call waits for (other streams
@@ -97,8 +109,9 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 
 /*
  * Executes a plan (the "execution function" of Fig. 1): reads `in`, writes
- * `out` (device pointers, each tcfft_plan_buffer_bytes() long, 16-byte
- * aligned; in == out allowed), enqueued asynchronously on `stream` (a
+ * `out` (device pointers of tcfft_plan_input_bytes() and
+ * tcfft_plan_output_bytes(), 16-byte aligned; in == out allowed when the
+ * buffer holds the larger of the two), enqueued asynchronously on `stream` (a
  * hipStream_t or NULL).  One exec per plan may be in flight at a time (the
  * plan's workspace is shared).
  * Errors: INVALID_ARG (null plan/pointer, misalignment), LAUNCH.
@@ -131,7 +144,7 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
  * order.  npasses equal to the plan's pass count is tcfft_exec.  `in` and
  * `out` must differ.  Errors: as tcfft_exec;
  * INVALID_ARG for npasses outside [1, passes] or in == out; UNSUPPORTED for
- * the FP32 comparator.
+ * the FP32 comparator and real plans.
  */
 tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
                                void* stream);
@@ -143,8 +156,14 @@ tcfft_status tcfft_plan_destroy(tcfft_plan plan);
 /* S such that out = DFT(in) * 2^-S (0 for NO_SCALE and the FP32 path); -1 for NULL. */
 int tcfft_plan_scale_log2(tcfft_plan plan);
 
-/* Bytes of one input (= output) buffer of the plan; 0 for NULL. */
+/* Bytes of the larger of the plan's input and output buffers (they are equal
+ * for complex plans); 0 for NULL. */
 size_t tcfft_plan_buffer_bytes(tcfft_plan plan);
+
+/* Bytes of the plan's input buffer and of its output buffer (they differ for
+ * real plans: M versus M+1 complex words per transform); 0 for NULL. */
+size_t tcfft_plan_input_bytes(tcfft_plan plan);
+size_t tcfft_plan_output_bytes(tcfft_plan plan);
 
 /* Device workspace bytes held by the plan; 0 for NULL. */
 size_t tcfft_plan_workspace_bytes(tcfft_plan plan);

@@ -11,6 +11,10 @@ Functions (tcFFT paper, Sec. 2.1 and Sec. 3.1):
   decimation in time, FP64, libm twiddles per index), batched.
 * :func:`fft2` -- rows then columns of a row-major array (Sec. 3.1).
 * :func:`merge` -- one merging process in the matrix form of Eq. (3).
+* :func:`rfft`, :func:`irfft` -- Eq. (1) for a real sequence (the spectrum's
+  first N/2 + 1 bins) and its inverse from those bins (Hermitian extension,
+  then the unnormalised inverse sum, real part); both by definition on top of
+  :func:`fft`.
 * :mod:`oracle.brute` -- an independent pure-numpy DFT (explicit sums / the DFT
   matrix), used only to pin the C routines on tiny inputs.
 
@@ -147,6 +151,29 @@ def fft2(x, sign: int = -1, threads: int = 0) -> np.ndarray:
 
 def merge(xin, sign: int = -1) -> np.ndarray:
     return default().merge(xin, sign)
+
+
+def rfft(x, threads: int = 0) -> np.ndarray:
+    """Eq. (1) for real x (..., N): bins 0..N/2 of the complex DFT of x + 0i."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[-1]
+    return fft(x.astype(np.complex128), -1, threads)[..., : n // 2 + 1]
+
+
+def irfft(X, n: int, threads: int = 0) -> np.ndarray:
+    """Unnormalised inverse of :func:`rfft`: the spectrum of a real sequence
+    is Hermitian, Y[N - k] = conj(Y[k]), so bins 0..N/2 fix all N; X[0] and
+    X[N/2] of a real sequence are real, their imaginary parts are dropped.
+    Returns sum_k Y[k] W_N^{-nk} (= N x for X = rfft(x))."""
+    X = np.asarray(X, dtype=np.complex128)
+    m = n // 2
+    assert X.shape[-1] == m + 1
+    Y = np.zeros(X.shape[:-1] + (n,), dtype=np.complex128)
+    Y[..., : m + 1] = X
+    Y[..., 0] = X[..., 0].real
+    Y[..., m] = X[..., m].real
+    Y[..., m + 1:] = np.conj(X[..., 1:m][..., ::-1])
+    return fft(Y, +1, threads).real
 
 
 def from_half(a: np.ndarray) -> np.ndarray:

@@ -98,4 +98,13 @@ void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mul
 void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s);
 void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s);
 
+// Real-input transforms around an M-point complex transform (N = 2M reals).
+// r2c_post: Z (batch x M words) -> X (batch x (M+1) words), tw[k] = W_N^k, k <= M.
+// c2r_pre:  X (batch x (M+1) words) -> Z' (batch x M words), tw[k] = W_N^-k.
+// Split precision: hi plane then lo plane of each buffer.
+void launch_r2c_post(const void* z, void* x, const float2* tw, int64_t M, int64_t batch,
+                     bool split, hipStream_t s);
+void launch_c2r_pre(const void* x, void* z, const float2* tw, int64_t M, int64_t batch,
+                    bool split, hipStream_t s);
+
 }  // namespace tcfft

@@ -95,6 +95,11 @@ struct PlanSpec {
   int scale = 0;
   size_t ws_bytes = 0;
   size_t buf_bytes = 0;
+  size_t in_bytes = 0, out_bytes = 0;
+  // real plans: N of the real transform (0 for complex plans); npts and the
+  // passes then describe the M = N/2 point complex transform inside
+  int64_t real_n = 0;
+  size_t zbuf_bytes = 0;  // the complex transform's side of the elementwise pass
 };
 
 tcfft_status col_choice(int L, int64_t inner, int cmax, bool split, bool xtw, bool tstore,
@@ -221,7 +226,8 @@ tcfft_status validate(const Desc& d) {
   if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
   if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
   if (d.prec < 0 || d.prec > 2) return TCFFT_ERR_INVALID_ARG;
-  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE))
+  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE |
+                            TCFFT_FLAG_REAL))
     return TCFFT_ERR_INVALID_ARG;
   if (d.nx <= 0 || d.ny <= 0) return TCFFT_ERR_INVALID_ARG;
   if (!is_pow2(d.nx) || !is_pow2(d.ny)) return TCFFT_ERR_UNSUPPORTED;
@@ -231,14 +237,45 @@ tcfft_status validate(const Desc& d) {
     if (d.nx < 16 || d.nx > kMaxColL || d.ny < 16 || d.ny > kMaxRowL) return TCFFT_ERR_UNSUPPORTED;
     if (d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
   }
+  if (d.flags & TCFFT_FLAG_REAL) {
+    if (d.rank != 1 || d.prec == TCFFT_PREC_FP32_RADIX2 || d.nx < 32) return TCFFT_ERR_UNSUPPORTED;
+  }
   const int64_t npts = d.nx * d.ny;
   if (d.batch > kMaxPointsPerPlan / npts) return TCFFT_ERR_UNSUPPORTED;
   return TCFFT_OK;
 }
 
+// The complex transform inside a real plan: M = N/2 points, same batch,
+// direction and precision.
+Desc complex_desc(const Desc& d) {
+  Desc c = d;
+  if (d.flags & TCFFT_FLAG_REAL) {
+    c.nx = d.nx / 2;
+    c.flags &= ~(unsigned)TCFFT_FLAG_REAL;
+  }
+  return c;
+}
+
 tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
   tcfft_status st = validate(d);
   if (st) return st;
+  if (d.flags & TCFFT_FLAG_REAL) {
+    // N reals = M complex words: the M-point complex plan, then (forward) or
+    // before it (inverse) one elementwise pass between it and the spectrum
+    PlanSpec ps;
+    if ((st = build_spec(complex_desc(d), ch, &ps))) return st;
+    const int64_t M = d.nx / 2;
+    const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
+    const size_t zb = (size_t)(M * d.batch) * elt, xb = (size_t)((M + 1) * d.batch) * elt;
+    ps.d = d;
+    ps.real_n = d.nx;
+    ps.zbuf_bytes = zb;
+    ps.in_bytes = d.dir == TCFFT_FORWARD ? zb : xb;
+    ps.out_bytes = d.dir == TCFFT_FORWARD ? xb : zb;
+    ps.buf_bytes = xb;
+    *out = ps;
+    return TCFFT_OK;
+  }
   PlanSpec ps;
   ps.d = d;
   ps.ch = ch;
@@ -246,6 +283,7 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
   const int64_t B = d.batch;
   const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
   ps.buf_bytes = (size_t)(ps.npts * B) * elt;
+  ps.in_bytes = ps.out_bytes = ps.buf_bytes;
   if (d.prec == TCFFT_PREC_FP32_RADIX2) {
     ps.ws_bytes = ps.buf_bytes;
     ps.scale = 0;
@@ -326,12 +364,16 @@ std::string describe(const PlanSpec& ps) {
   std::string s;
   std::snprintf(b, sizeof b,
                 "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
-                "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"workspace_bytes\":%zu,"
+                "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"input_bytes\":%zu,\"output_bytes\":%zu,"
+                "\"workspace_bytes\":%zu,\"real\":%lld,\"real_kernel\":\"%s\","
                 "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
                 "\"tuned_us\":%.2f,\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
                 ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
-                precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.ws_bytes, ps.ch.row_nt, ps.ch.cmax,
+                precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.in_bytes, ps.out_bytes,
+                ps.ws_bytes + ps.zbuf_bytes, (long long)ps.real_n,
+                ps.real_n == 0 ? "" : (ps.d.dir == TCFFT_FORWARD ? "r2c_post" : "c2r_pre"),
+                ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
                 ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
                 ps.tuned_us);
@@ -399,6 +441,8 @@ struct tcfft_plan_s {
   void* fimg = nullptr;     // radix-16 A operands (pass-independent: one scale variant)
   void* ws = nullptr;
   float2* r2tw = nullptr;   // FP32 radix-2 comparator: W_N^m
+  void* zbuf = nullptr;     // real plans: the complex transform's input or output
+  float2* rtw = nullptr;    // real plans: W_N^{dir k}, k <= M
   std::vector<void*> allocs;
 };
 
@@ -531,6 +575,14 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
     }
     if (st) break;
     if ((st = dev_alloc(p, ps.ws_bytes, &p->ws))) break;
+    if (ps.real_n > 0) {
+      const int64_t M = ps.real_n / 2;
+      if ((st = dev_alloc(p, ps.zbuf_bytes, &p->zbuf))) break;
+      void* t = nullptr;
+      if ((st = dev_alloc(p, (size_t)(M + 1) * sizeof(float2), &t))) break;
+      p->rtw = (float2*)t;
+      launch_gen_twiddles(p->rtw, M + 1, ps.real_n, 1, sgn, s);
+    }
   } while (false);
   if (!st && hipGetLastError() != hipSuccess) st = TCFFT_ERR_LAUNCH;
   if (hipStreamSynchronize(s) != hipSuccess && !st) st = TCFFT_ERR_LAUNCH;
@@ -648,6 +700,34 @@ tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s
     }
   }
   return TCFFT_OK;
+}
+
+// Real plans: the M-point complex transform from the input into zbuf, then the
+// spectrum pass (forward); or the pass into zbuf, then the transform (inverse).
+void launch_real_step(const tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  const PlanSpec& ps = p->spec;
+  const bool split = ps.d.prec == TCFFT_PREC_SPLIT_FP16;
+  if (ps.d.dir == TCFFT_FORWARD)
+    launch_r2c_post(p->zbuf, out, p->rtw, ps.npts, ps.d.batch, split, s);
+  else
+    launch_c2r_pre(in, p->zbuf, p->rtw, ps.npts, ps.d.batch, split, s);
+}
+
+tcfft_status exec_real(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  tcfft_status st;
+  if (p->spec.d.dir == TCFFT_FORWARD) {
+    if ((st = exec_impl(p, in, p->zbuf, s))) return st;
+    launch_real_step(p, nullptr, out, s);
+  } else {
+    launch_real_step(p, in, nullptr, s);
+    if ((st = exec_impl(p, p->zbuf, out, s))) return st;
+  }
+  if (hipGetLastError() != hipSuccess) return TCFFT_ERR_LAUNCH;
+  return TCFFT_OK;
+}
+
+tcfft_status exec_any(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
+  return p->spec.real_n > 0 ? exec_real(p, in, out, s) : exec_impl(p, in, out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -869,20 +949,35 @@ namespace {
 tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void* const* out,
                             int njobs, hipStream_t s) {
   std::vector<Job> jobs;
+  std::vector<int> post;  // real forward jobs: their spectrum pass runs after the group
   jobs.reserve(njobs);
   for (int j = 0; j < njobs; ++j) {
-    const PlanSpec& ps = plans[j]->spec;
+    tcfft_plan_s* p = plans[j];
+    const PlanSpec& ps = p->spec;
     if (ps.d.prec == TCFFT_PREC_FP16 && ps.ch.chunk > 0 && ps.ch.chunk < ps.d.batch &&
-        plans[j]->dp.size() > 1) {
+        p->dp.size() > 1) {
       // a chunked plan's workspace holds one chunk: it runs on its own
-      tcfft_status st = exec_impl(plans[j], in[j], out[j], s);
+      tcfft_status st = exec_any(p, in[j], out[j], s);
       if (st) return st;
       continue;
     }
-    jobs.push_back(Job{plans[j], in[j], const_cast<void*>(out[j]), ps.d.batch, plans[j]->ws});
+    const void* ji = in[j];
+    void* jo = out[j];
+    if (ps.real_n > 0 && ps.d.dir == TCFFT_FORWARD) {
+      jo = p->zbuf;
+      post.push_back(j);
+    } else if (ps.real_n > 0) {
+      launch_real_step(p, in[j], nullptr, s);
+      ji = p->zbuf;
+    }
+    jobs.push_back(Job{p, ji, jo, ps.d.batch, p->ws});
   }
-  if (jobs.empty()) return TCFFT_OK;
-  return tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), s, nullptr, 0, nullptr);
+  if (!jobs.empty()) {
+    tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), s, nullptr, 0, nullptr);
+    if (st) return st;
+  }
+  for (int j : post) launch_real_step(plans[j], nullptr, out[j], s);
+  return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
 }
 
 // ---------------------------------------------------------------------------
@@ -1111,7 +1206,8 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
   Choice ch;
   bool tuned = false;
   double tuned_us = 0.0;
-  if ((st = choose(d, &ch, &tuned, &tuned_us))) return st;
+  // a real plan shares the tuned choice of its complex transform
+  if ((st = choose(complex_desc(d), &ch, &tuned, &tuned_us))) return st;
   if ((st = build_spec(d, ch, &ps))) return st;
   ps.tuned = tuned;
   ps.tuned_us = tuned_us;
@@ -1157,14 +1253,15 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream) {
   if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
-  return exec_impl(plan, in, out, (hipStream_t)stream);
+  return exec_any(plan, in, out, (hipStream_t)stream);
 }
 
 tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
                                void* stream) {
   if (!plan || !in || !out || in == out) return TCFFT_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
-  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0)
+    return TCFFT_ERR_UNSUPPORTED;
   if (npasses < 1 || npasses > (int)plan->dp.size()) return TCFFT_ERR_INVALID_ARG;
   return exec_impl(plan, in, out, (hipStream_t)stream, npasses);
 }
@@ -1192,12 +1289,18 @@ int tcfft_plan_scale_log2(tcfft_plan plan) { return plan ? plan->spec.scale : -1
 
 size_t tcfft_plan_buffer_bytes(tcfft_plan plan) { return plan ? plan->spec.buf_bytes : 0; }
 
-size_t tcfft_plan_workspace_bytes(tcfft_plan plan) { return plan ? plan->spec.ws_bytes : 0; }
+size_t tcfft_plan_input_bytes(tcfft_plan plan) { return plan ? plan->spec.in_bytes : 0; }
+
+size_t tcfft_plan_output_bytes(tcfft_plan plan) { return plan ? plan->spec.out_bytes : 0; }
+
+size_t tcfft_plan_workspace_bytes(tcfft_plan plan) {
+  return plan ? plan->spec.ws_bytes + plan->spec.zbuf_bytes : 0;
+}
 
 int tcfft_plan_num_launches(tcfft_plan plan) {
   if (!plan) return -1;
   if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return ilog2(plan->spec.npts);
-  return (int)plan->spec.passes.size();
+  return (int)plan->spec.passes.size() + (plan->spec.real_n > 0 ? 1 : 0);
 }
 
 int tcfft_plan_describe(tcfft_plan plan, char* buf, size_t len) {

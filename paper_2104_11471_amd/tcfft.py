@@ -22,6 +22,7 @@ PREC_FP32_RADIX2 = 2
 FLAG_NO_SCALE = 1
 FLAG_NO_GRAPH = 2
 FLAG_TUNE = 4
+FLAG_REAL = 8
 _PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_FP16,
          "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2}
 
@@ -31,7 +32,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "
 # every symbol include/tcfft.h declares
 EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", "tcfft_exec_many",
            "tcfft_exec_passes", "tcfft_plan_destroy", "tcfft_plan_scale_log2",
-           "tcfft_plan_buffer_bytes", "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
+           "tcfft_plan_buffer_bytes", "tcfft_plan_input_bytes", "tcfft_plan_output_bytes",
+           "tcfft_plan_workspace_bytes", "tcfft_plan_num_launches", "tcfft_plan_describe",
            "tcfft_plan_dry_run", "tcfft_status_string", "tcfft_version", "tcfft_tune_candidates",
            "tcfft_tune_cache_size", "tcfft_tune_cache_save", "tcfft_tune_cache_load",
            "tcfft_tune_cache_clear", "tcfft_server_create", "tcfft_server_prepare",
@@ -71,6 +73,10 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_plan_scale_log2.argtypes = [vp]
     lib.tcfft_plan_buffer_bytes.argtypes = [vp]
     lib.tcfft_plan_buffer_bytes.restype = ctypes.c_size_t
+    lib.tcfft_plan_input_bytes.argtypes = [vp]
+    lib.tcfft_plan_input_bytes.restype = ctypes.c_size_t
+    lib.tcfft_plan_output_bytes.argtypes = [vp]
+    lib.tcfft_plan_output_bytes.restype = ctypes.c_size_t
     lib.tcfft_plan_workspace_bytes.argtypes = [vp]
     lib.tcfft_plan_workspace_bytes.restype = ctypes.c_size_t
     lib.tcfft_plan_num_launches.argtypes = [vp]
@@ -158,7 +164,13 @@ class Plan:
       * split: ``float16`` of shape ``(2, batch, *dims, 2)`` -- hi plane then lo
         plane, value = hi + 2^-11 lo;
       * fp32_radix2: ``float32`` of shape ``(batch, n, 2)``.
-    The output holds DFT(x) * 2^-scale_log2 in the same layout."""
+    The output holds DFT(x) * 2^-scale_log2 in the same layout.
+
+    Real plans (``flags`` with FLAG_REAL, 1D, N = 2M): the real side is
+    ``float16`` of shape ``(batch, N)`` (split: ``(2, batch, N)``), the
+    spectrum side ``(batch, M + 1, 2)`` (split: ``(2, batch, M + 1, 2)``) with
+    bins 0..M.  FORWARD maps real -> spectrum, INVERSE spectrum -> real (N x
+    the sequence, times 2^-scale_log2)."""
 
     def __init__(self, dims, batch: int, direction: int = FORWARD, precision="fp16",
                  flags: int = 0):
@@ -200,10 +212,36 @@ class Plan:
         lib.tcfft_plan_describe(self._h, buf, len(buf))
         return json.loads(buf.value.decode())
 
+    @property
+    def input_bytes(self) -> int:
+        return int(lib.tcfft_plan_input_bytes(self._h))
+
+    @property
+    def output_bytes(self) -> int:
+        return int(lib.tcfft_plan_output_bytes(self._h))
+
+    @property
+    def real(self) -> bool:
+        return bool(self.flags & FLAG_REAL)
+
+    def _side(self, real_side: bool) -> tuple:
+        if real_side:
+            core = (self.batch, self.dims[0])
+        elif self.real:
+            core = (self.batch, self.dims[0] // 2 + 1, 2)
+        else:
+            core = (self.batch, *self.dims, 2)
+        return (2, *core) if self.precision == PREC_SPLIT_FP16 else core
+
+    def in_shape(self) -> tuple:
+        return self._side(self.real and self.direction == FORWARD)
+
+    def out_shape(self) -> tuple:
+        return self._side(self.real and self.direction == INVERSE)
+
     def shape(self) -> tuple:
-        if self.precision == PREC_SPLIT_FP16:
-            return (2, self.batch, *self.dims, 2)
-        return (self.batch, *self.dims, 2)
+        """The input shape (equal to the output shape for complex plans)."""
+        return self.in_shape()
 
     def dtype(self):
         import torch
@@ -211,7 +249,11 @@ class Plan:
 
     def empty(self, device=None):
         import torch
-        return torch.empty(self.shape(), dtype=self.dtype(), device=device or "cuda")
+        return torch.empty(self.in_shape(), dtype=self.dtype(), device=device or "cuda")
+
+    def empty_out(self, device=None):
+        import torch
+        return torch.empty(self.out_shape(), dtype=self.dtype(), device=device or "cuda")
 
     def _check(self, t, name):
         import torch
@@ -219,9 +261,10 @@ class Plan:
             raise ValueError(f"{name} must be a CUDA (HIP) tensor")
         if t.dtype != self.dtype() or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {self.dtype()} tensor")
-        if t.numel() * t.element_size() != self.buffer_bytes:
+        need = self.input_bytes if name == "input" else self.output_bytes
+        if t.numel() * t.element_size() != need:
             raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, "
-                             f"the plan needs {self.buffer_bytes}")
+                             f"the plan needs {need}")
 
     def exec_raw(self, in_ptr: int, out_ptr: int, stream_ptr: int) -> None:
         st = lib.tcfft_exec(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
@@ -233,7 +276,7 @@ class Plan:
         import torch
         self._check(x, "input")
         if out is None:
-            out = torch.empty_like(x)
+            out = torch.empty(self.out_shape(), dtype=x.dtype, device=x.device)
         self._check(out, "output")
         s = stream if stream is not None else torch.cuda.current_stream(x.device)
         self.exec_raw(x.data_ptr(), out.data_ptr(), s.cuda_stream)

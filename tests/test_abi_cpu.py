@@ -168,3 +168,30 @@ def test_tune_cache_file_errors(tc, tmp_path):
     tc.tune_cache_save(str(tmp_path / "out.txt"))
     assert "r1_4096x1_b8_p0 512 64" in (tmp_path / "out.txt").read_text()
     tc.tune_cache_clear()
+
+
+@pytest.mark.parametrize("n", [32, 4096, 65536, 1 << 24])
+def test_real_plan_layout(tc, n):
+    """A real plan is the N/2-point complex plan plus one elementwise pass;
+    its buffers are M and M+1 words per transform."""
+    m, b = n // 2, 3
+    c = tc.dry_run((m,), b)
+    for dirn, kern, ib, ob in [(tc.FORWARD, "r2c_post", m, m + 1), (tc.INVERSE, "c2r_pre", m + 1, m)]:
+        d = tc.dry_run((n,), b, dirn, flags=tc.FLAG_REAL)
+        assert d["real"] == n and d["real_kernel"] == kern
+        assert d["dims"] == [n]
+        assert [(p["kernel"], p["L"]) for p in d["passes"]] == [(p["kernel"], p["L"]) for p in c["passes"]]
+        assert d["scale_log2"] == c["scale_log2"]
+        assert d["input_bytes"] == b * ib * 4 and d["output_bytes"] == b * ob * 4
+        assert d["buffer_bytes"] == b * (m + 1) * 4
+        assert d["workspace_bytes"] == c["workspace_bytes"] + b * m * 4
+    s = tc.dry_run((n,), b, precision="split", flags=tc.FLAG_REAL)
+    assert s["input_bytes"] == b * m * 8 and s["output_bytes"] == b * (m + 1) * 8
+    assert tc.dry_run((m,), b)["real"] == 0
+
+
+@pytest.mark.parametrize("dims,prec", [((16,), "fp16"), ((64, 64), "fp16"), ((256,), "fp32")])
+def test_real_plan_rejects(tc, dims, prec):
+    with pytest.raises(tc.TcfftError) as e:
+        tc.dry_run(dims, 1, precision=prec, flags=tc.FLAG_REAL)
+    assert e.value.status == 2

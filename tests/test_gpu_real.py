@@ -1,0 +1,155 @@
+"""Real-input transforms (R2C forward, C2R inverse) on the GPU against the
+oracle's rfft/irfft: single-pass, two-pass and three-pass complex cores, FP16
+and split precision, the round trip, in-place use and grouped execution."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_11471_amd import inputs
+from tests.gpu_util import FP16_TOL, SPLIT_TOL, log
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [32, 64, 512, 4096, 32768, 65536, 1 << 21, 1 << 24]
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2104_11471_amd import tcfft
+    return tcfft
+
+
+def batch_for(n):
+    return max(1, min(5, (1 << 22) // n))
+
+
+def real_input(n, batch, prec, seed):
+    """N reals per transform as M complex words (the library's real layout)."""
+    m = n // 2
+    if prec == "split":
+        hi, lo = inputs.to_split(inputs.uniform_f64((batch, m), seed))
+        host = np.stack([hi.reshape(batch, n), lo.reshape(batch, n)])
+        val = hi.reshape(batch, n).astype(np.float64) + 2.0 ** -11 * lo.reshape(batch, n).astype(np.float64)
+    else:
+        host = inputs.uniform((batch, m), seed).reshape(batch, n)
+        val = host.astype(np.float64)
+    return host, val
+
+
+def spectrum_input(n, batch, prec, seed):
+    m = n // 2
+    if prec == "split":
+        hi, lo = inputs.to_split(inputs.uniform_f64((batch, m + 1), seed))
+        return np.stack([hi, lo]), oracle.from_split(hi, lo)
+    x = inputs.uniform((batch, m + 1), seed)
+    return x, oracle.from_half(x)
+
+
+def read_spectrum(out, prec):
+    y = out.cpu().numpy().astype(np.float64)
+    if prec == "split":
+        return (y[0, ..., 0] + 2.0 ** -11 * y[1, ..., 0]) + 1j * (y[0, ..., 1] + 2.0 ** -11 * y[1, ..., 1])
+    return y[..., 0] + 1j * y[..., 1]
+
+
+def read_real(out, prec):
+    y = out.cpu().numpy().astype(np.float64)
+    return y[0] + 2.0 ** -11 * y[1] if prec == "split" else y
+
+
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("n", SIZES)
+def test_r2c_parity(tc, n, prec):
+    import torch
+    b = batch_for(n)
+    log(f"case r2c n={n} batch={b} prec={prec}")
+    p = tc.Plan((n,), b, tc.FORWARD, prec, flags=tc.FLAG_REAL)
+    assert p.in_shape()[-1] == n and p.out_shape()[-2:] == (n // 2 + 1, 2)
+    host, val = real_input(n, b, prec, 21)
+    out = p(torch.from_numpy(host).cuda())
+    torch.cuda.synchronize()
+    y = read_spectrum(out, prec) * 2.0 ** p.scale_log2
+    e = oracle.rel_l2(y, oracle.rfft(val))
+    log(f"  max rel L2 = {e.max():.3e}")
+    assert e.max() <= (SPLIT_TOL if prec == "split" else FP16_TOL)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("n", SIZES)
+def test_c2r_parity(tc, n, prec):
+    """A general spectrum (non-real X[0], X[M] included: their imaginary parts
+    are ignored, as for the oracle)."""
+    import torch
+    b = batch_for(n)
+    log(f"case c2r n={n} batch={b} prec={prec}")
+    p = tc.Plan((n,), b, tc.INVERSE, prec, flags=tc.FLAG_REAL)
+    host, X = spectrum_input(n, b, prec, 22)
+    out = p(torch.from_numpy(np.ascontiguousarray(host)).cuda())
+    torch.cuda.synchronize()
+    y = read_real(out, prec) * 2.0 ** p.scale_log2
+    e = oracle.rel_l2(y, oracle.irfft(X, n))
+    log(f"  max rel L2 = {e.max():.3e}")
+    assert e.max() <= (SPLIT_TOL if prec == "split" else FP16_TOL)
+
+
+@pytest.mark.parametrize("n", [64, 4096, 1 << 20])
+def test_round_trip(tc, n):
+    """C2R(R2C(x)) = N x 2^-(S_f + S_i), on the device in place."""
+    import torch
+    b = 3
+    log(f"case real round trip n={n}")
+    f = tc.Plan((n,), b, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
+    i = tc.Plan((n,), b, tc.INVERSE, "fp16", flags=tc.FLAG_REAL)
+    host, val = real_input(n, b, "fp16", 23)
+    buf = torch.zeros(b * (n // 2 + 1) * 2, dtype=torch.float16, device="cuda")
+    buf[: b * n] = torch.from_numpy(host).cuda().reshape(-1)
+    f.exec_raw(buf.data_ptr(), buf.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    i.exec_raw(buf.data_ptr(), buf.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    y = buf[: b * n].reshape(b, n).cpu().numpy().astype(np.float64)
+    y *= 2.0 ** (f.scale_log2 + i.scale_log2)
+    e = oracle.rel_l2(y, n * val)
+    log(f"  max rel L2 = {e.max():.3e}")
+    assert e.max() <= 2 * FP16_TOL
+
+
+def test_real_tone(tc):
+    """A cosine tone: all energy in one bin (closed form N/2)."""
+    import torch
+    n, f0 = 4096, 37
+    p = tc.Plan((n,), 1, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
+    x = np.cos(2 * np.pi * f0 * np.arange(n) / n).astype(np.float16)[None, :]
+    y = read_spectrum(p(torch.from_numpy(x).cuda()), "fp16") * 2.0 ** p.scale_log2
+    assert abs(y[0, f0] - n / 2) < 1e-2 * n / 2
+    y[0, f0] = 0
+    assert np.max(np.abs(y)) < 2e-3 * n / 2
+
+
+def test_real_grouped_matches_single(tc):
+    """Real plans (both directions) mixed with a complex plan in one grouped
+    call give each job's single-exec bits."""
+    import torch
+    pf = tc.Plan((4096,), 3, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
+    pi = tc.Plan((65536,), 2, tc.INVERSE, "fp16", flags=tc.FLAG_REAL)
+    pc = tc.Plan((1024,), 4)
+    xs = [torch.from_numpy(real_input(4096, 3, "fp16", 1)[0]).cuda(),
+          torch.from_numpy(spectrum_input(65536, 2, "fp16", 2)[0]).cuda(),
+          torch.from_numpy(inputs.uniform((4, 1024), 3)).cuda()]
+    plans = [pf, pi, pc]
+    singles = [p(x) for p, x in zip(plans, xs)]
+    outs = [p.empty_out() for p in plans]
+    tc.exec_many(plans, xs, outs)
+    torch.cuda.synchronize()
+    for a, o in zip(singles, outs):
+        assert torch.equal(a.view(torch.int16), o.view(torch.int16))
+
+
+def test_real_describe(tc):
+    p = tc.Plan((8192,), 2, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
+    d = p.describe()
+    assert d["real"] == 8192 and d["real_kernel"] == "r2c_post"
+    assert [q["L"] for q in d["passes"]] == [4096]
+    assert p.input_bytes == 2 * 4096 * 4 and p.output_bytes == 2 * 4097 * 4
+    assert p.num_launches == 2
+    x, o = p.empty(), p.empty_out()
+    assert tc.lib.tcfft_exec_passes(p.handle, x.data_ptr(), o.data_ptr(), 1, None) == 2
