@@ -203,6 +203,60 @@ def other_workloads(stream) -> dict:
             log(f"{key}: {out[key]}")
             del xd, yd, p
             torch.cuda.empty_cache()
+    out.update(real_workloads(stream))
+    return out
+
+
+def real_workloads(stream) -> dict:
+    """Real-input transforms (R2C forward, C2R inverse) of N reals stored as
+    N/2 complex words, the spectrum as N/2 + 1 bins: timing and row-0 accuracy
+    against the oracle's rfft / irfft.  Algorithmic bytes are one read of the
+    input and one write of the output.  Not part of `value`."""
+    import torch
+    import oracle
+    from paper_2104_11471_amd import inputs, tcfft
+    out = {}
+    cases = [(8192, 16384, "fp16"), (8192, 16384, "split"), (32768, 4096, "fp16"),
+             (1 << 21, 64, "fp16")]
+    for n, batch, prec in cases:
+        m = n // 2
+        split = prec == "split"
+        for dirn, name in ((tcfft.FORWARD, "r2c"), (tcfft.INVERSE, "c2r")):
+            p = tcfft.Plan((n,), batch, dirn, prec, flags=tcfft.FLAG_REAL)
+            words = m if dirn == tcfft.FORWARD else m + 1
+            if split:
+                hi, lo = inputs.to_split(inputs.uniform_f64((batch, words), 5))
+                host = np.stack([hi, lo])
+            else:
+                host = inputs.uniform((batch, words), 5)
+            xd = torch.from_numpy(host).cuda().reshape(p.in_shape())
+            yd = torch.empty(p.out_shape(), dtype=torch.float16, device=xd.device)
+            p(xd, yd, stream=stream)
+            dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
+            y = yd.cpu().numpy().astype(np.float64)
+            if split:
+                x0 = host[0][0].astype(np.float64) + 2.0 ** -11 * host[1][0].astype(np.float64)
+                y0 = y[0][0] + 2.0 ** -11 * y[1][0]
+            else:
+                x0 = host[0].astype(np.float64)
+                y0 = y[0]
+            x0c = x0[..., 0] + 1j * x0[..., 1]
+            if dirn == tcfft.FORWARD:
+                ref = oracle.rfft(x0.reshape(n))
+                got = (y0[..., 0] + 1j * y0[..., 1]) * 2.0 ** p.scale_log2
+            else:
+                ref = oracle.irfft(x0c, n)
+                got = y0 * 2.0 ** p.scale_log2
+            bpe = 8 if split else 4
+            alg = bpe * batch * (2 * m + 1)
+            key = f"{name}_{n}x{batch}_{prec}"
+            out[key] = {"us": round(dt * 1e6, 1), "gbs_alg": round(alg / dt / 1e9, 1),
+                        "hbm_frac_alg": round(alg / dt / 1e9 / HBM_PEAK_GBS, 4),
+                        "launches": p.num_launches, "real_kernel": p.describe()["real_kernel"],
+                        "rel_l2_row0": float(oracle.rel_l2(got, ref, axis=None))}
+            log(f"{key}: {out[key]}")
+            del xd, yd, p
+            torch.cuda.empty_cache()
     return out
 
 
@@ -336,7 +390,7 @@ def main():
     dom_bytes = 8.0 * TOTAL_POINTS
     dk = plans[dom].describe()["passes"][0]
     kname = (f"row_kernel<{dk['L']}, {dk['radices'][0] if dk['radices'][0] != 16 else 1}, "
-             f"{dk['NT']}, false, false>")
+             f"{dk['NT']}, false, false, 0>")
     per[dom]["choice"] = plans[dom].describe()["choice"]
     achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -4,7 +4,7 @@
 namespace tcfft {
 
 #define ROWK(L_, R_, N_)                                                             \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore) {      \
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore && !k.real) {\
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true>;                          \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true>;                      \
@@ -19,7 +19,7 @@ namespace tcfft {
 
 // Transposed-store variants (second pass of a four-step transform).
 #define ROWKT(L_, R_, N_)                                                            \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && k.tstore) {       \
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && k.tstore && !k.real) {\
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true, true>;                    \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true, true>;                \

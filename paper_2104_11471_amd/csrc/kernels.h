@@ -50,6 +50,7 @@ struct KernelKey {
   int split;   // 0 FP16, 1 split hi+lo
   int xtw;     // column kernel: apply the extra inter-pass twiddle
   int tstore;  // column kernel: transposed store (row of L contiguous outputs)
+  int real = 0;  // row kernel: 1 real forward (spectrum epilogue), 2 real inverse (prologue)
 };
 
 // Header of one grouped launch, in device memory: job j of the group owns
@@ -78,6 +79,7 @@ bool find_col_kernels_small(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_256(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_large(const KernelKey& key, KernelFns* out);
 bool find_big_kernels(const KernelKey& key, KernelFns* out);
+bool find_real_row_kernels(const KernelKey& key, KernelFns* out);
 // Returns the single-launch kernel for `key`, or nullptr.
 KernelFn find_kernel(const KernelKey& key);
 // Dynamic LDS bytes the kernel needs.

@@ -59,6 +59,9 @@ __device__ __forceinline__ u4 gld4(const uint32_t* ptr) {
   return *(const TCFFT_GLOBAL u4*)(ptr);
 }
 __device__ __forceinline__ void gst4(uint32_t* ptr, u4 v) { *(TCFFT_GLOBAL u4*)(ptr) = v; }
+__device__ __forceinline__ uint32_t gld1(const uint32_t* ptr) {
+  return *(const TCFFT_GLOBAL uint32_t*)(ptr);
+}
 __device__ __forceinline__ void gst1(uint32_t* ptr, uint32_t v) {
   *(TCFFT_GLOBAL uint32_t*)(ptr) = v;
 }
@@ -181,7 +184,8 @@ __device__ __forceinline__ TwB load_twb(const float2* tw, int g, int mul) {
 }
 
 // Radix-R0 stage on the vector ALU, HBM -> LDS (always the first stage).
-template <class G, bool SPLIT>
+// SRCL: the input is already in LDS (natural order), read and rewritten in place.
+template <class G, bool SPLIT, bool SRCL = false>
 __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, int valid,
                                              int64_t g0) {
   constexpr int L = G::L, R0 = G::R0, P0 = G::P0;
@@ -201,14 +205,20 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
     const int tau = col0 / P0;
     const int lo0 = col0 % P0;
     // lines past the end of the batch read line 0 of the tile (never stored)
-    const int taul = tau < valid ? tau : 0;
+    const int taul = (SRCL || tau < valid) ? tau : 0;
     u4 hh[R0], ll[R0];
 #pragma unroll
     for (int d = 0; d < R0; ++d) {
       const int p = taul * L + d * P0 + lo0;
-      hh[d] = gld4(kp.in + g0 + p);
-      if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + g0 + p);
-      else ll[d] = u4{0, 0, 0, 0};
+      if constexpr (SRCL) {
+        hh[d] = lds_ld4(lds, p);
+        if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, p);
+        else ll[d] = u4{0, 0, 0, 0};
+      } else {
+        hh[d] = gld4(kp.in + g0 + p);
+        if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + g0 + p);
+        else ll[d] = u4{0, 0, 0, 0};
+      }
     }
     float2 a[R0];
 #pragma unroll
@@ -285,15 +295,23 @@ __device__ __forceinline__ void row_stage16_load(const KParams& kp, int valid, i
 // index, so the lane writes output k of lines tau0..tau0+3 as one 16-byte
 // group at b (q L) + k s_out + (line mod q) (line = global line index, q lines
 // per transform): the pass writes X[k1 + q k2] with no gather.
-template <class G, int P, bool SRCG, bool SPLIT, bool PRE = false, bool TT = false>
+//
+// KEEP (last stage only): the results go to LDS in natural order instead of
+// HBM, for an epilogue that reads whole lines.  The stage reads digit-reversed
+// positions that other lanes overwrite, so the results wait in registers until
+// every lane of the workgroup has read its inputs.
+template <class G, int P, bool SRCG, bool SPLIT, bool PRE = false, bool TT = false,
+          bool KEEP = false>
 __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, int valid,
                                             int64_t g0, const FOps& f,
                                             const Row16Regs<G>* pre = nullptr) {
   constexpr int L = G::L, R0 = G::R0, S = G::S;
   constexpr int TM = P > 1 ? L / (16 * P) : 1;  // W_{16P}^e = W_L^{e TM}
+  static_assert(!KEEP || (P == 1 && !SRCG && !TT && L / 16 >= 4), "natural-order LDS result");
   uint32_t* ldsl = lds + G::PTS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
+  u4 kh[KEEP ? G::QPW : 1][4], kl[KEEP && SPLIT ? G::QPW : 1][4];
   TwB B;
   if constexpr (P > 1) B = load_twb(kp.tw, g, TM);
 #pragma unroll
@@ -377,6 +395,12 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
         lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
         if constexpr (SPLIT) lds_st4(ldsl, p, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
       }
+    } else if constexpr (KEEP) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        kh[qq][j] = u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]};
+        if constexpr (SPLIT) kl[qq][j] = u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]};
+      }
     } else {
       // natural output index of (row, col): tau*L + klow + (L/16)*row
       if constexpr (TT) {
@@ -439,6 +463,20 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
       }
     }
   }
+  if constexpr (KEEP) {
+    __syncthreads();  // every lane has read its inputs
+#pragma unroll
+    for (int qq = 0; qq < G::QPW; ++qq) {
+      const int col0 = 4 * c16 + 64 * (wave * G::QPW + qq);
+      const int tau = col0 / (L / 16), klow0 = col0 % (L / 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = tau * L + klow0 + (L / 16) * (4 * g + j);
+        lds_st4(lds, p, kh[qq][j]);
+        if constexpr (SPLIT) lds_st4(ldsl, p, kl[qq][j]);
+      }
+    }
+  }
 }
 
 // Whether the radix-R0 stage and the first radix-16 stage of a row pass run
@@ -462,7 +500,7 @@ struct RowFused {
 // operands of R0 matrix-core DFTs (one per radix-R0 output k), whose results
 // take the twiddle W_{16P}^{k1 lo} and go to LDS at the positions the unfused
 // first radix-16 stage writes.
-template <class G, bool SPLIT>
+template <class G, bool SPLIT, bool SRCL = false>
 __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds, int valid,
                                                 int64_t g0, const FOps& f) {
   constexpr int L = G::L, R0 = G::R0;
@@ -489,16 +527,23 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
     const int sq = (wave * ITF + it) * 16 + c16;
     const int tau = sq / (P / 4);
     const int lo0 = 4 * (sq % (P / 4));
-    const int taul = (G::TPB > 1 && tau >= valid) ? 0 : tau;  // past the batch: line 0
+    // past the batch: line 0 (LDS source: the lane's own positions, in place)
+    const int taul = (!SRCL && G::TPB > 1 && tau >= valid) ? 0 : tau;
     u4 hh[R0][4], ll[R0][4];
 #pragma unroll
     for (int d = 0; d < R0; ++d)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int p = taul * L + d * P0 + (4 * g + i) * P + lo0;
-        hh[d][i] = gld4(kp.in + g0 + p);
-        if constexpr (SPLIT) ll[d][i] = gld4(kp.in + kp.in_plane + g0 + p);
-        else ll[d][i] = u4{0, 0, 0, 0};
+        if constexpr (SRCL) {
+          hh[d][i] = lds_ld4(lds, p);
+          if constexpr (SPLIT) ll[d][i] = lds_ld4(ldsl, p);
+          else ll[d][i] = u4{0, 0, 0, 0};
+        } else {
+          hh[d][i] = gld4(kp.in + g0 + p);
+          if constexpr (SPLIT) ll[d][i] = gld4(kp.in + kp.in_plane + g0 + p);
+          else ll[d][i] = u4{0, 0, 0, 0};
+        }
       }
     float2 at[R0][4];  // W_L^{k (lo0 + t)}
 #pragma unroll
@@ -559,40 +604,226 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
   }
 }
 
-template <class G, int E, bool SPLIT, bool TT = false>
+template <class G, int E, bool SPLIT, bool TT = false, bool KEEP = false>
 __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds, int valid,
                                                 int64_t g0, const FOps& f) {
   // radix-16 stages with stride 16^E, 16^(E-1), ..., 1, all reading LDS
-  row_stage16<G, pow16(E), false, SPLIT, false, E == 0 && TT>(kp, lds, valid, g0, f);
+  row_stage16<G, pow16(E), false, SPLIT, false, E == 0 && TT, E == 0 && KEEP>(kp, lds, valid, g0,
+                                                                              f);
   if constexpr (E > 0) {
     __syncthreads();
-    row_stages_from<G, E - 1, SPLIT, TT>(kp, lds, valid, g0, f);
+    row_stages_from<G, E - 1, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Real-input transforms fused into a row pass of M = L points.  An N = 2M
+// point real sequence is read as M complex words z[m] = x[2m] + i x[2m+1];
+// with Z its M-point DFT and W = W_N (the table kp.xtw_lo holds W^{dir k},
+// k <= M), the even/odd split of Eq. 2 (N1 = 2) gives for the spectrum
+//   X[k] = ((Z[k] + conj Z[M-k]) - i W^k (Z[k] - conj Z[M-k])) / 2,  k <= M,
+// and for the inverse
+//   Z'[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]),      k < M,
+// whose inverse M-point DFT is N (x[2m] + i x[2m+1]).  Index k and M - k come
+// from the same pair of inputs, and W^{M-k} = -conj(W^k), so one lane handles
+// both.  Spectrum lines hold M + 1 words.
+
+// Work split of the real epilogue / prologue: item (line, j), j < M/2, covers
+// the index pair (j, M - j) (j = 0 pairs bin 0 with bin M); the self-paired
+// middle index M/2 of each line is a separate short loop.  Thread t takes
+// items it = 0 .. ITER-1 with, for M/2 >= NT, j = t + NT (it mod NQ) and
+// line = it / NQ, else j = t mod M/2 and line = t / (M/2) + it NT / (M/2): the
+// line and the high part of j are compile-time per item, and the twiddle
+// W^j = W^t * W^{NT q} is one table load per thread times a uniform value.
+// Items go U per thread with every load of a group issued before its first use.
+template <class G>
+struct RealLoop {
+  static constexpr int M = G::L, HM = M / 2, NT = G::NT;
+  static constexpr int ITER = G::TPB * HM / NT;
+  static constexpr int U = ITER < 8 ? ITER : 8;
+  static constexpr bool WIDE = HM >= NT;       // a line spans NQ items of a thread
+  static constexpr int NQ = WIDE ? HM / NT : 1;
+  static constexpr int LPI = WIDE ? 1 : NT / HM;  // lines per item step
+  static_assert(ITER >= 1 && ITER * NT == G::TPB * HM && ITER % U == 0, "item split");
+  __device__ static int line(int it) {
+    return WIDE ? it / NQ : (int)threadIdx.x / HM + it * LPI;
+  }
+  __device__ static int j(int it) {
+    return WIDE ? (int)threadIdx.x + NT * (it % NQ) : (int)threadIdx.x & (HM - 1);
+  }
+  // W^{NT (j div NT)}: uniform across the workgroup (1 when it does not vary)
+  __device__ static float2 wq(const float2* tab, int it) {
+    if constexpr (WIDE) return tld(tab, NT * (it % NQ));
+    return make_float2(1.f, 0.f);
+  }
+  // W^j from the thread's W^{j mod NT} (wt) and the uniform factor
+  __device__ static float2 w(float2 wt, float2 q, int it) {
+    if constexpr (WIDE) return it % NQ == 0 ? wt : cmul(wt, q);
+    return wt;
+  }
+  __device__ static float2 wthread(const float2* tab) {
+    return tld(tab, WIDE ? (int)threadIdx.x : ((int)threadIdx.x & (HM - 1)));
+  }
+};
+
+// Both members of an index pair from one twiddle product.  Forward, with
+// a = Z[k], b = Z[M-k], e = a + conj b, d = a - conj b, v = -i W^k d:
+//   X[k] = (e + v) / 2,   X[M-k] = conj(e - v) / 2
+// (swapping a and b conjugates e, negates conj d, and W^{M-k} = -conj W^k).
+// Inverse, with a = X[k], c = X[M-k], e = a + conj c, t = i W^-k (a - conj c):
+//   Z'[k] = e + t,        Z'[M-k] = conj(e - t).
+__device__ __forceinline__ void real_spec(float2 a, float2 b, float2 w, float2& xk, float2& xm) {
+  const float2 h = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));  // e / 2
+  const float2 d = make_float2(a.x - b.x, a.y + b.y);
+  const float2 v = cmul(make_float2(0.5f * w.x, 0.5f * w.y), make_float2(d.y, -d.x));  // v / 2
+  xk = make_float2(h.x + v.x, h.y + v.y);
+  xm = make_float2(h.x - v.x, v.y - h.y);
+}
+__device__ __forceinline__ void real_zpre(float2 a, float2 c, float2 w, float2& zk, float2& zm) {
+  const float2 e = make_float2(a.x + c.x, a.y - c.y);
+  const float2 d = cmul(make_float2(a.x - c.x, a.y + c.y), w);
+  const float2 t = make_float2(-d.y, d.x);  // i W^-k (a - conj c)
+  zk = make_float2(e.x + t.x, e.y + t.y);
+  zm = make_float2(e.x - t.x, t.y - e.y);
+}
+
+// R2C epilogue: Z of `valid` lines in LDS (natural order) -> X in HBM.
+template <class G, bool SPLIT>
+__device__ __forceinline__ void real_post(const KParams& kp, const uint32_t* lds, int valid,
+                                          int64_t t0) {
+  using R = RealLoop<G>;
+  constexpr int M = R::M, HM = R::HM, U = R::U;
+  const uint32_t* ldsl = lds + G::PTS;
+  uint32_t* const oh = kp.out + t0 * (int64_t)(M + 1);
+  uint32_t* const ol = oh + kp.out_plane;
+  auto rd = [&](int p) { return value<SPLIT>(lds_ld1(lds, p), SPLIT ? lds_ld1(ldsl, p) : 0u); };
+  auto st = [&](uint32_t off, float2 v) {
+    uint32_t h = 0, l = 0;
+    emit<SPLIT>(v.x, v.y, h, l);
+    gst1(oh + off, h);
+    if constexpr (SPLIT) gst1(ol + off, l);
+  };
+  const float2 wt = R::wthread(kp.xtw_lo);
+#pragma unroll
+  for (int it0 = 0; it0 < R::ITER; it0 += U) {
+    float2 a[U], b[U], q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int line = R::line(it0 + u), j = R::j(it0 + u);
+      a[u] = rd(line * M + j);
+      b[u] = rd(line * M + ((M - j) & (M - 1)));
+      q[u] = R::wq(kp.xtw_lo, it0 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int line = R::line(it0 + u), j = R::j(it0 + u);
+      if (line < valid) {
+        float2 xk, xm;
+        real_spec(a[u], b[u], R::w(wt, q[u], it0 + u), xk, xm);
+        const uint32_t off = (uint32_t)(line * (M + 1) + j);
+        st(off, xk);
+        st(off + (uint32_t)(M - 2 * j), xm);  // X[M-j]
+      }
+    }
+  }
+  const float2 wm = tld(kp.xtw_lo, HM);
+  for (int line = threadIdx.x; line < valid; line += G::NT) {
+    const float2 z = rd(line * M + HM);
+    float2 xk, xm;
+    real_spec(z, z, wm, xk, xm);
+    st((uint32_t)(line * (M + 1) + HM), xk);
+  }
+}
+
+// C2R prologue: X of `valid` lines in HBM -> Z' in LDS (natural order).  The
+// imaginary parts of X[0] and X[M] are ignored (a real sequence has them 0).
+template <class G, bool SPLIT>
+__device__ __forceinline__ void real_pre(const KParams& kp, uint32_t* lds, int valid, int64_t t0) {
+  using R = RealLoop<G>;
+  constexpr int M = R::M, HM = R::HM, U = R::U;
+  uint32_t* ldsl = lds + G::PTS;
+  const uint32_t* const xh = kp.in + t0 * (int64_t)(M + 1);
+  const uint32_t* const xl = xh + kp.in_plane;
+  auto rd = [&](uint32_t off) { return value<SPLIT>(gld1(xh + off), SPLIT ? gld1(xl + off) : 0u); };
+  auto st = [&](int p, float2 v) {
+    uint32_t h = 0, l = 0;
+    emit<SPLIT>(v.x, v.y, h, l);
+    lds_st1(lds, p, h);
+    if constexpr (SPLIT) lds_st1(ldsl, p, l);
+  };
+  const float2 wt = R::wthread(kp.xtw_lo);
+#pragma unroll
+  for (int it0 = 0; it0 < R::ITER; it0 += U) {
+    float2 a[U], c[U], q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int line = R::line(it0 + u);
+      const int j = R::j(it0 + u);
+      line = line < valid ? line : 0;  // past the batch: line 0, never stored
+      const uint32_t off = (uint32_t)(line * (M + 1) + j);
+      a[u] = rd(off);
+      c[u] = rd(off + (uint32_t)(M - 2 * j));
+      q[u] = R::wq(kp.xtw_lo, it0 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int line = R::line(it0 + u), j = R::j(it0 + u);
+      if (line < valid) {
+        if (j == 0) {  // X[0] and X[M]: real parts only; Z'[M] does not exist
+          a[u].y = 0.f;
+          c[u].y = 0.f;
+        }
+        float2 zk, zm;
+        real_zpre(a[u], c[u], R::w(wt, q[u], it0 + u), zk, zm);
+        st(line * M + j, zk);
+        if (j != 0) st(line * M + M - j, zm);
+      }
+    }
+  }
+  const float2 wm = tld(kp.xtw_lo, HM);
+  for (int line = threadIdx.x; line < valid; line += G::NT) {
+    const float2 x = rd((uint32_t)(line * (M + 1) + HM));
+    float2 zk, zm;
+    real_zpre(x, x, wm, zk, zm);
+    st(line * M + HM, zk);
   }
 }
 
 // One workgroup's share of a row pass: workgroup index wg of the pass.
-template <int L, int R0, int NT, bool SPLIT, bool TT = false>
+// RK: 0 complex; 1 real forward (spectrum epilogue); 2 real inverse (prologue).
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
 __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = RowGeom<L, R0, NT>;
+  static_assert(RK == 0 || (!TT && G::S >= 1 && L >= 64), "real variants");
+  constexpr bool KEEP = RK == 1, SRCL = RK == 2;
   const int64_t t0 = wg * G::TPB;
   const int64_t rem = kp.ntrans - t0;
   const int valid = rem < G::TPB ? (int)rem : G::TPB;
   const int64_t g0 = t0 * L;
   const FOps f = load_fops<SPLIT>(kp.fimg);
+  if constexpr (SRCL) {
+    real_pre<G, SPLIT>(kp, lds, valid, t0);
+    __syncthreads();
+  }
   if constexpr (RowFused<G>::value) {
-    row_stage_fused<G, SPLIT>(kp, lds, valid, g0, f);
+    row_stage_fused<G, SPLIT, SRCL>(kp, lds, valid, g0, f);
     __syncthreads();
-    row_stages_from<G, G::S - 2, SPLIT, TT>(kp, lds, valid, g0, f);
+    row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
   } else if constexpr (R0 > 1) {
-    row_stage_r0<G, SPLIT>(kp, lds, valid, g0);
+    row_stage_r0<G, SPLIT, SRCL>(kp, lds, valid, g0);
     __syncthreads();
-    row_stages_from<G, G::S - 1, SPLIT, TT>(kp, lds, valid, g0, f);
+    row_stages_from<G, G::S - 1, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
   } else {
-    row_stage16<G, pow16(G::S - 1), true, SPLIT>(kp, lds, valid, g0, f);
+    static_assert(!KEEP || G::S > 1, "the epilogue follows an LDS stage");
+    row_stage16<G, pow16(G::S - 1), !SRCL, SPLIT>(kp, lds, valid, g0, f);
     if constexpr (G::S > 1) {
       __syncthreads();
-      row_stages_from<G, G::S - 2, SPLIT, TT>(kp, lds, valid, g0, f);
+      row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
     }
+  }
+  if constexpr (KEEP) {
+    __syncthreads();
+    real_post<G, SPLIT>(kp, lds, valid, t0);
   }
 }
 
@@ -639,13 +870,13 @@ __device__ __forceinline__ void row_pipe(const KParams& kp, uint32_t* lds) {
   }
 }
 
-template <int L, int R0, int NT, bool SPLIT, bool TT = false>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
 __global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
   extern __shared__ uint32_t lds[];
-  if constexpr (!TT && RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
+  if constexpr (!TT && RK == 0 && RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
     row_pipe<L, R0, NT, SPLIT>(kp, lds);
   else
-    row_body<L, R0, NT, SPLIT, TT>(kp, blockIdx.x, lds);
+    row_body<L, R0, NT, SPLIT, TT, RK>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -1068,7 +1299,7 @@ __device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
 // FP16 row tiles use 64 KB of LDS, so two workgroups share a CU: the register
 // budget is capped to match (the persistent loop otherwise keeps enough
 // loop-invariant addresses live to drop to one workgroup per CU).
-template <int L, int R0, int NT, bool SPLIT, bool TT = false>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
 __global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
   CGroupHdr* h = (CGroupHdr*)hdr;
@@ -1079,7 +1310,7 @@ __global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const Grou
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
     const KParams kp = load_job(jobs, j);
-    row_body<L, R0, NT, SPLIT, TT>(kp, w - prefix[j], lds);
+    row_body<L, R0, NT, SPLIT, TT, RK>(kp, w - prefix[j], lds);
     __syncthreads();  // the next tile's first stage rewrites LDS
   }
 }

@@ -6,7 +6,7 @@ namespace tcfft {
 bool find_kernels(const KernelKey& k, KernelFns* out) {
   return find_row_kernels(k, out) || find_col_kernels_small(k, out) ||
          find_col_kernels_256(k, out) || find_col_kernels_large(k, out) ||
-         find_big_kernels(k, out);
+         find_big_kernels(k, out) || find_real_row_kernels(k, out);
 }
 
 KernelFn find_kernel(const KernelKey& k) {

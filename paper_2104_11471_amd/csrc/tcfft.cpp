@@ -99,7 +99,8 @@ struct PlanSpec {
   // real plans: N of the real transform (0 for complex plans); npts and the
   // passes then describe the M = N/2 point complex transform inside
   int64_t real_n = 0;
-  size_t zbuf_bytes = 0;  // the complex transform's side of the elementwise pass
+  bool real_fused = false;  // the real step runs inside the (single) row pass
+  size_t zbuf_bytes = 0;  // unfused: the complex transform's side of the elementwise pass
 };
 
 tcfft_status col_choice(int L, int64_t inner, int cmax, bool split, bool xtw, bool tstore,
@@ -270,6 +271,18 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     ps.d = d;
     ps.real_n = d.nx;
     ps.zbuf_bytes = zb;
+    // single-pass sizes: the spectrum step runs inside the row pass (an
+    // epilogue forward, a prologue inverse), so the data crosses HBM once
+    if (ps.passes.size() == 1 && ps.passes[0].key.kind == K_ROW) {
+      KernelKey k = ps.passes[0].key;
+      k.NT = 256;
+      k.real = d.dir == TCFFT_FORWARD ? 1 : 2;
+      if (find_kernel(k)) {
+        ps.passes[0].key = k;
+        ps.real_fused = true;
+        ps.zbuf_bytes = 0;
+      }
+    }
     ps.in_bytes = d.dir == TCFFT_FORWARD ? zb : xb;
     ps.out_bytes = d.dir == TCFFT_FORWARD ? xb : zb;
     ps.buf_bytes = xb;
@@ -372,7 +385,7 @@ std::string describe(const PlanSpec& ps) {
                 ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
                 precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.in_bytes, ps.out_bytes,
                 ps.ws_bytes + ps.zbuf_bytes, (long long)ps.real_n,
-                ps.real_n == 0 ? "" : (ps.d.dir == TCFFT_FORWARD ? "r2c_post" : "c2r_pre"),
+                ps.real_n == 0 ? "" : ps.real_fused ? "fused" : (ps.d.dir == TCFFT_FORWARD ? "r2c_post" : "c2r_pre"),
                 ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
                 ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
@@ -399,11 +412,11 @@ std::string describe(const PlanSpec& ps) {
     std::snprintf(b, sizeof b,
                   "%s{\"kernel\":\"%s\",\"L\":%d,\"radices\":%s,\"C\":%d,\"NT\":%d,\"grid\":%lld,"
                   "\"lds\":%zu,\"xtw\":%d,\"tstore\":%d,\"scale\":%d,\"src\":%d,\"dst\":%d,"
-                  "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld}",
+                  "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld,\"real\":%d}",
                   i ? "," : "", p.key.kind == K_ROW ? "row" : (p.key.kind == K_BIG ? "big" : "col"),
                   p.key.L, rad.c_str(), p.key.C,
                   p.key.NT, (long long)p.grid, p.lds, p.key.xtw, p.key.tstore, p.scale, p.src,
-                  p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod);
+                  p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod, p.key.real);
     s += b;
   }
   s += "]}";
@@ -638,6 +651,11 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.blocks_log2 = sp.blocks > 0 ? ilog2(sp.blocks) : 0;
   kp.q_log2 = ilog2(sp.q);
   kp.xdiv_log2 = ilog2(sp.xdiv);
+  if (sp.key.real) {  // spectrum lines hold M + 1 words; the row pass reads W_N from xtw_lo
+    if (split && sp.key.real == 1) kp.out_plane = (ps.npts + 1) * batch;
+    if (split && sp.key.real == 2) kp.in_plane = (ps.npts + 1) * batch;
+    kp.xtw_lo = p->rtw;
+  }
   return kp;
 }
 
@@ -715,6 +733,7 @@ void launch_real_step(const tcfft_plan_s* p, const void* in, void* out, hipStrea
 
 tcfft_status exec_real(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
   tcfft_status st;
+  if (p->spec.real_fused) return exec_impl(p, in, out, s);
   if (p->spec.d.dir == TCFFT_FORWARD) {
     if ((st = exec_impl(p, in, p->zbuf, s))) return st;
     launch_real_step(p, nullptr, out, s);
@@ -963,10 +982,11 @@ tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void
     }
     const void* ji = in[j];
     void* jo = out[j];
-    if (ps.real_n > 0 && ps.d.dir == TCFFT_FORWARD) {
+    const bool step = ps.real_n > 0 && !ps.real_fused;
+    if (step && ps.d.dir == TCFFT_FORWARD) {
       jo = p->zbuf;
       post.push_back(j);
-    } else if (ps.real_n > 0) {
+    } else if (step) {
       launch_real_step(p, in[j], nullptr, s);
       ji = p->zbuf;
     }
@@ -1300,7 +1320,7 @@ size_t tcfft_plan_workspace_bytes(tcfft_plan plan) {
 int tcfft_plan_num_launches(tcfft_plan plan) {
   if (!plan) return -1;
   if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return ilog2(plan->spec.npts);
-  return (int)plan->spec.passes.size() + (plan->spec.real_n > 0 ? 1 : 0);
+  return (int)plan->spec.passes.size() + (plan->spec.real_n > 0 && !plan->spec.real_fused ? 1 : 0);
 }
 
 int tcfft_plan_describe(tcfft_plan plan, char* buf, size_t len) {

@@ -170,21 +170,24 @@ def test_tune_cache_file_errors(tc, tmp_path):
     tc.tune_cache_clear()
 
 
-@pytest.mark.parametrize("n", [32, 4096, 65536, 1 << 24])
+@pytest.mark.parametrize("n", [32, 64, 128, 4096, 32768, 65536, 1 << 24])
 def test_real_plan_layout(tc, n):
     """A real plan is the N/2-point complex plan plus one elementwise pass;
     its buffers are M and M+1 words per transform."""
     m, b = n // 2, 3
     c = tc.dry_run((m,), b)
-    for dirn, kern, ib, ob in [(tc.FORWARD, "r2c_post", m, m + 1), (tc.INVERSE, "c2r_pre", m + 1, m)]:
+    fused = 64 <= m <= 16384  # single row pass: the real step is its epilogue / prologue
+    for dirn, kern, ib, ob, rk in [(tc.FORWARD, "r2c_post", m, m + 1, 1),
+                                   (tc.INVERSE, "c2r_pre", m + 1, m, 2)]:
         d = tc.dry_run((n,), b, dirn, flags=tc.FLAG_REAL)
-        assert d["real"] == n and d["real_kernel"] == kern
+        assert d["real"] == n and d["real_kernel"] == ("fused" if fused else kern)
         assert d["dims"] == [n]
         assert [(p["kernel"], p["L"]) for p in d["passes"]] == [(p["kernel"], p["L"]) for p in c["passes"]]
+        assert [p["real"] for p in d["passes"]] == ([rk] if fused else [0] * len(c["passes"]))
         assert d["scale_log2"] == c["scale_log2"]
         assert d["input_bytes"] == b * ib * 4 and d["output_bytes"] == b * ob * 4
         assert d["buffer_bytes"] == b * (m + 1) * 4
-        assert d["workspace_bytes"] == c["workspace_bytes"] + b * m * 4
+        assert d["workspace_bytes"] == c["workspace_bytes"] + (0 if fused else b * m * 4)
     s = tc.dry_run((n,), b, precision="split", flags=tc.FLAG_REAL)
     assert s["input_bytes"] == b * m * 8 and s["output_bytes"] == b * (m + 1) * 8
     assert tc.dry_run((m,), b)["real"] == 0

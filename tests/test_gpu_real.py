@@ -10,7 +10,7 @@ from tests.gpu_util import FP16_TOL, SPLIT_TOL, log
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [32, 64, 512, 4096, 32768, 65536, 1 << 21, 1 << 24]
+SIZES = [32, 64, 128, 256, 512, 1024, 4096, 8192, 16384, 32768, 65536, 1 << 21, 1 << 24]
 
 
 @pytest.fixture(scope="module")
@@ -92,6 +92,24 @@ def test_c2r_parity(tc, n, prec):
     assert e.max() <= (SPLIT_TOL if prec == "split" else FP16_TOL)
 
 
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("n,batch", [(128, 513), (256, 300), (2048, 37), (32768, 7)])
+def test_real_many_lines(tc, n, batch, prec):
+    """Fused row passes over several workgroups of lines with a ragged last
+    workgroup, both directions."""
+    import torch
+    log(f"case real lines n={n} batch={batch} prec={prec}")
+    tol = SPLIT_TOL if prec == "split" else FP16_TOL
+    f = tc.Plan((n,), batch, tc.FORWARD, prec, flags=tc.FLAG_REAL)
+    host, val = real_input(n, batch, prec, 24)
+    y = read_spectrum(f(torch.from_numpy(host).cuda()), prec) * 2.0 ** f.scale_log2
+    assert oracle.rel_l2(y, oracle.rfft(val)).max() <= tol
+    i = tc.Plan((n,), batch, tc.INVERSE, prec, flags=tc.FLAG_REAL)
+    host, X = spectrum_input(n, batch, prec, 25)
+    y = read_real(i(torch.from_numpy(np.ascontiguousarray(host)).cuda()), prec) * 2.0 ** i.scale_log2
+    assert oracle.rel_l2(y, oracle.irfft(X, n)).max() <= tol
+
+
 @pytest.mark.parametrize("n", [64, 4096, 1 << 20])
 def test_round_trip(tc, n):
     """C2R(R2C(x)) = N x 2^-(S_f + S_i), on the device in place."""
@@ -147,9 +165,10 @@ def test_real_grouped_matches_single(tc):
 def test_real_describe(tc):
     p = tc.Plan((8192,), 2, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
     d = p.describe()
-    assert d["real"] == 8192 and d["real_kernel"] == "r2c_post"
+    assert d["real"] == 8192 and d["real_kernel"] == "fused"
     assert [q["L"] for q in d["passes"]] == [4096]
     assert p.input_bytes == 2 * 4096 * 4 and p.output_bytes == 2 * 4097 * 4
-    assert p.num_launches == 2
+    assert p.num_launches == 1
+    assert tc.Plan((1 << 16,), 1, tc.FORWARD, "fp16", flags=tc.FLAG_REAL).num_launches == 3
     x, o = p.empty(), p.empty_out()
     assert tc.lib.tcfft_exec_passes(p.handle, x.data_ptr(), o.data_ptr(), 1, None) == 2
