@@ -74,9 +74,12 @@ enum {
  * Creates a plan (Sec. 3.1 and Fig. 1: the plan picks the merging kernels once,
  * the execution function runs them many times).
  *   out        receives the plan handle (set to NULL on failure)
- *   rank       1 or 2
- *   dims       rank values: {N} or {nx, ny}; powers of two.  1D: 16 <= N <= 2^27.
+ *   rank       1, 2 or 3
+ *   dims       rank values: {N}, {nx, ny} or {nx, ny, nz} (last index
+ *              contiguous); powers of two.  1D: 16 <= N <= 2^27.
  *              2D: 16 <= nx <= 2048, 16 <= ny <= 16384.
+ *              3D: 16 <= nx, ny <= 2048, 16 <= nz <= 16384 (a row pass over
+ *              nz, then column passes over ny and over nx).
  *   batch      number of transforms, >= 1 (batch * points <= 2^31 per plan)
  *   dir        TCFFT_FORWARD or TCFFT_INVERSE
  *   precision  TCFFT_PREC_*

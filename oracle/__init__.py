@@ -11,6 +11,8 @@ Functions (tcFFT paper, Sec. 2.1 and Sec. 3.1):
   decimation in time, FP64, libm twiddles per index), batched.
 * :func:`fft2` -- rows then columns of a row-major array (Sec. 3.1).
 * :func:`merge` -- one merging process in the matrix form of Eq. (3).
+* :func:`fft3` -- Eq. (1) over three indices of a row-major array, evaluated
+  as 1D transforms of :func:`fft` along each axis (the sum is separable).
 * :func:`rfft`, :func:`irfft` -- Eq. (1) for a real sequence (the spectrum's
   first N/2 + 1 bins) and its inverse from those bins (Hermitian extension,
   then the unnormalised inverse sum, real part); both by definition on top of
@@ -151,6 +153,18 @@ def fft2(x, sign: int = -1, threads: int = 0) -> np.ndarray:
 
 def merge(xin, sign: int = -1) -> np.ndarray:
     return default().merge(xin, sign)
+
+
+def fft3(x, sign: int = -1, threads: int = 0) -> np.ndarray:
+    """Batched 3D DFT over the last three axes: the triple sum factors into
+    1D transforms along z (last axis), then y, then x."""
+    z = np.asarray(x, dtype=np.complex128)
+    assert z.ndim >= 3
+    for ax in (-1, -2, -3):
+        t = np.ascontiguousarray(np.moveaxis(z, ax, -1))
+        t = fft(t.reshape(-1, t.shape[-1]), sign, threads).reshape(t.shape)
+        z = np.moveaxis(t, -1, ax)
+    return np.ascontiguousarray(z)
 
 
 def rfft(x, threads: int = 0) -> np.ndarray:

@@ -59,6 +59,7 @@ struct PassSpec {
   int64_t s_in = 0, s_out = 0, blocks = 0, in_outer = 0, out_outer = 0, q = 1, qstride = 0;
   // extra twiddle
   int64_t xmod = 0, xdiv = 1;
+  int64_t outer_per_batch = 1;  // column kernel: [L][inner] blocks per transform
   // buffers: 0 = user in, 1 = user out, 2 = workspace
   int src = 0, dst = 1;
   int scale = 0;  // this pass's scale exponent
@@ -66,7 +67,7 @@ struct PassSpec {
 
 struct Desc {
   int rank = 1;
-  int64_t nx = 0, ny = 1;
+  int64_t nx = 0, ny = 1, nz = 1;
   int64_t batch = 0;
   int dir = -1;
   int prec = 0;
@@ -197,6 +198,7 @@ tcfft_status add_col_pass(PlanSpec& ps, int L, int64_t inner, int64_t outer, int
   p.xmod = xmod;
   p.xdiv = xdiv;
   p.grid = outer * p.blocks;
+  p.outer_per_batch = outer / ps.d.batch;
   p.lds = kernel_lds_bytes(p.key);
   p.src = src;
   p.dst = dst;
@@ -223,25 +225,31 @@ std::vector<int> long_split(int64_t n) {
 }
 
 tcfft_status validate(const Desc& d) {
-  if (d.rank != 1 && d.rank != 2) return TCFFT_ERR_INVALID_ARG;
+  if (d.rank < 1 || d.rank > 3) return TCFFT_ERR_INVALID_ARG;
   if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
   if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
   if (d.prec < 0 || d.prec > 2) return TCFFT_ERR_INVALID_ARG;
   if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE |
                             TCFFT_FLAG_REAL))
     return TCFFT_ERR_INVALID_ARG;
-  if (d.nx <= 0 || d.ny <= 0) return TCFFT_ERR_INVALID_ARG;
-  if (!is_pow2(d.nx) || !is_pow2(d.ny)) return TCFFT_ERR_UNSUPPORTED;
+  if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return TCFFT_ERR_INVALID_ARG;
+  if (!is_pow2(d.nx) || !is_pow2(d.ny) || !is_pow2(d.nz)) return TCFFT_ERR_UNSUPPORTED;
   if (d.rank == 1) {
     if (d.nx < 16 || d.nx > ((int64_t)1 << 27)) return TCFFT_ERR_UNSUPPORTED;
-  } else {
+  } else if (d.rank == 2) {
     if (d.nx < 16 || d.nx > kMaxColL || d.ny < 16 || d.ny > kMaxRowL) return TCFFT_ERR_UNSUPPORTED;
+    if (d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  } else {
+    if (d.nx < 16 || d.nx > kMaxColL || d.ny < 16 || d.ny > kMaxColL || d.nz < 16 ||
+        d.nz > kMaxRowL)
+      return TCFFT_ERR_UNSUPPORTED;
     if (d.prec == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
   }
   if (d.flags & TCFFT_FLAG_REAL) {
     if (d.rank != 1 || d.prec == TCFFT_PREC_FP32_RADIX2 || d.nx < 32) return TCFFT_ERR_UNSUPPORTED;
   }
-  const int64_t npts = d.nx * d.ny;
+  if (d.nx * d.ny > kMaxPointsPerPlan / d.nz) return TCFFT_ERR_UNSUPPORTED;
+  const int64_t npts = d.nx * d.ny * d.nz;
   if (d.batch > kMaxPointsPerPlan / npts) return TCFFT_ERR_UNSUPPORTED;
   return TCFFT_OK;
 }
@@ -292,7 +300,7 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
   PlanSpec ps;
   ps.d = d;
   ps.ch = ch;
-  ps.npts = d.nx * d.ny;
+  ps.npts = d.nx * d.ny * d.nz;
   const int64_t B = d.batch;
   const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
   ps.buf_bytes = (size_t)(ps.npts * B) * elt;
@@ -353,12 +361,23 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
       }
       ps.ws_bytes = ps.buf_bytes;
     }
-  } else {
+  } else if (d.rank == 2) {
     const int64_t nx = d.nx, ny = d.ny;
     // rows: B*nx contiguous ny-point transforms; then columns: B blocks of
     // [nx][ny], strided nx-point transforms, in place in the output
     st = add_row_pass(ps, (int)ny, B * nx, 0, 1);
     if (!st) st = add_col_pass(ps, (int)nx, ny, B, nx * ny, nx * ny, ny, ny, 0, false, 0, 1, 1, 1);
+  } else {
+    // the 3D DFT is separable: rows of nz (contiguous), then ny-point
+    // transforms over the B*nx planes [ny][nz], then nx-point transforms over
+    // the B blocks [nx][ny*nz]; the column passes run in place in the output
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    st = add_row_pass(ps, (int)nz, B * nx * ny, 0, 1);
+    if (!st)
+      st = add_col_pass(ps, (int)ny, nz, B * nx, ny * nz, ny * nz, nz, nz, 0, false, 0, 1, 1, 1);
+    if (!st)
+      st = add_col_pass(ps, (int)nx, ny * nz, B, ps.npts, ps.npts, ny * nz, ny * nz, 0, false, 0, 1,
+                        1, 1);
   }
   if (st) return st;
   if (d.prec == TCFFT_PREC_FP16 && ch.chunk > 0 && ch.chunk < B && ps.ws_bytes > 0)
@@ -376,13 +395,14 @@ std::string describe(const PlanSpec& ps) {
   char b[1024];
   std::string s;
   std::snprintf(b, sizeof b,
-                "{\"rank\":%d,\"dims\":[%lld%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
+                "{\"rank\":%d,\"dims\":[%lld%s%s%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"input_bytes\":%zu,\"output_bytes\":%zu,"
                 "\"workspace_bytes\":%zu,\"real\":%lld,\"real_kernel\":\"%s\","
                 "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
                 "\"tuned_us\":%.2f,\"passes\":[",
-                ps.d.rank, (long long)ps.d.nx, ps.d.rank == 2 ? "," : "",
-                ps.d.rank == 2 ? std::to_string(ps.d.ny).c_str() : "", (long long)ps.d.batch, ps.d.dir,
+                ps.d.rank, (long long)ps.d.nx, ps.d.rank >= 2 ? "," : "",
+                ps.d.rank >= 2 ? std::to_string(ps.d.ny).c_str() : "", ps.d.rank == 3 ? "," : "",
+                ps.d.rank == 3 ? std::to_string(ps.d.nz).c_str() : "", (long long)ps.d.batch, ps.d.dir,
                 precs[ps.d.prec], ps.scale, ps.buf_bytes, ps.in_bytes, ps.out_bytes,
                 ps.ws_bytes + ps.zbuf_bytes, (long long)ps.real_n,
                 ps.real_n == 0 ? "" : ps.real_fused ? "fused" : (ps.d.dir == TCFFT_FORWARD ? "r2c_post" : "c2r_pre"),
@@ -629,7 +649,7 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
     *grid = (kp.ntrans + sp.tpb - 1) / sp.tpb;
   } else {
     kp.ntrans = 0;
-    *grid = sp.blocks * batch;
+    *grid = sp.blocks * batch * sp.outer_per_batch;
   }
   kp.tw = dpp.tw;
   kp.fimg = p->fimg;
@@ -1010,8 +1030,12 @@ std::map<std::string, std::pair<Choice, double>> g_tune;
 
 std::string tune_key(const Desc& d) {
   char b[160];
-  std::snprintf(b, sizeof b, "r%d_%lldx%lld_b%d_p%d", d.rank, (long long)d.nx, (long long)d.ny,
-                ilog2(d.batch), d.prec);
+  if (d.rank == 3)
+    std::snprintf(b, sizeof b, "r3_%lldx%lldx%lld_b%d_p%d", (long long)d.nx, (long long)d.ny,
+                  (long long)d.nz, ilog2(d.batch), d.prec);
+  else
+    std::snprintf(b, sizeof b, "r%d_%lldx%lld_b%d_p%d", d.rank, (long long)d.nx, (long long)d.ny,
+                  ilog2(d.batch), d.prec);
   return b;
 }
 
@@ -1021,10 +1045,10 @@ std::vector<Choice> candidates_base(const Desc& d);
 // multi-pass FP16 candidate.
 std::vector<Choice> candidates(const Desc& d) {
   std::vector<Choice> base = candidates_base(d);
-  const bool multipass = d.rank == 2 || d.nx > kMaxRowL;
+  const bool multipass = d.rank >= 2 || d.nx > kMaxRowL;
   if (!multipass || d.prec != TCFFT_PREC_FP16) return base;
   std::vector<Choice> out = base;
-  const int64_t per = d.nx * d.ny * 4;  // bytes of one FP16 transform
+  const int64_t per = d.nx * d.ny * d.nz * 4;  // bytes of one FP16 transform
   for (int64_t mb : {64, 128}) {
     const int64_t c = std::max<int64_t>(1, (mb << 20) / per);
     if (c >= d.batch) continue;
@@ -1142,7 +1166,7 @@ tcfft_status choose(const Desc& d, Choice* ch, bool* tuned, double* tuned_us) {
   if (cands.size() <= 1) return TCFFT_OK;
   // tune on at most 2^26 points per buffer (same kernels, fewer workgroups)
   Desc dt = d;
-  const int64_t npts = d.nx * d.ny;
+  const int64_t npts = d.nx * d.ny * d.nz;
   dt.batch = std::max<int64_t>(1, std::min<int64_t>(d.batch, ((int64_t)1 << 26) / npts));
   size_t bytes = 0;
   std::vector<PlanSpec> specs;
@@ -1246,9 +1270,10 @@ tcfft_status tcfft_plan_create(tcfft_plan* out, int rank, const int64_t* dims, i
   *out = nullptr;
   Desc d;
   d.rank = rank;
-  if (rank != 1 && rank != 2) return TCFFT_ERR_INVALID_ARG;
+  if (rank < 1 || rank > 3) return TCFFT_ERR_INVALID_ARG;
   d.nx = dims[0];
-  d.ny = rank == 2 ? dims[1] : 1;
+  d.ny = rank >= 2 ? dims[1] : 1;
+  d.nz = rank == 3 ? dims[2] : 1;
   d.batch = batch;
   d.dir = dir;
   d.prec = precision;
@@ -1330,11 +1355,12 @@ int tcfft_plan_describe(tcfft_plan plan, char* buf, size_t len) {
 
 int tcfft_plan_dry_run(int rank, const int64_t* dims, int64_t batch, int dir, int precision,
                        unsigned flags, char* buf, size_t len) {
-  if (!dims || (rank != 1 && rank != 2)) return -(int)TCFFT_ERR_INVALID_ARG;
+  if (!dims || rank < 1 || rank > 3) return -(int)TCFFT_ERR_INVALID_ARG;
   Desc d;
   d.rank = rank;
   d.nx = dims[0];
-  d.ny = rank == 2 ? dims[1] : 1;
+  d.ny = rank >= 2 ? dims[1] : 1;
+  d.nz = rank == 3 ? dims[2] : 1;
   d.batch = batch;
   d.dir = dir;
   d.prec = precision;
@@ -1347,11 +1373,12 @@ int tcfft_plan_dry_run(int rank, const int64_t* dims, int64_t batch, int dir, in
 
 int tcfft_tune_candidates(int rank, const int64_t* dims, int64_t batch, int precision, char* buf,
                           size_t len) {
-  if (!dims || (rank != 1 && rank != 2)) return -(int)TCFFT_ERR_INVALID_ARG;
+  if (!dims || rank < 1 || rank > 3) return -(int)TCFFT_ERR_INVALID_ARG;
   Desc d;
   d.rank = rank;
   d.nx = dims[0];
-  d.ny = rank == 2 ? dims[1] : 1;
+  d.ny = rank >= 2 ? dims[1] : 1;
+  d.nz = rank == 3 ? dims[2] : 1;
   d.batch = batch;
   d.prec = precision;
   tcfft_status st = validate(d);

@@ -135,7 +135,7 @@ def test_null_arguments(tc):
     assert lib.tcfft_exec_many(None, None, None, 0, None) == 0
     assert lib.tcfft_exec_passes(None, None, None, 1, None) == 1
     h = ctypes.c_void_p()
-    assert lib.tcfft_plan_create(ctypes.byref(h), 3, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
+    assert lib.tcfft_plan_create(ctypes.byref(h), 4, (ctypes.c_int64 * 4)(16, 16, 16, 16), 1, -1, 0, 0) == 1
     assert lib.tcfft_plan_create(None, 1, (ctypes.c_int64 * 1)(16), 1, -1, 0, 0) == 1
 
 
@@ -197,4 +197,35 @@ def test_real_plan_layout(tc, n):
 def test_real_plan_rejects(tc, dims, prec):
     with pytest.raises(tc.TcfftError) as e:
         tc.dry_run(dims, 1, precision=prec, flags=tc.FLAG_REAL)
+    assert e.value.status == 2
+
+
+@pytest.mark.parametrize("prec", ["fp16", "split"])
+@pytest.mark.parametrize("dims", [(16, 16, 16), (64, 64, 64), (128, 32, 256), (2048, 16, 16),
+                                  (16, 2048, 16384)])
+def test_plan_3d(tc, dims, prec):
+    """A row pass over nz, then column passes over ny and nx, in place in the output."""
+    b = 2
+    d = tc.dry_run(dims, b, precision=prec)
+    assert d["dims"] == list(dims)
+    assert [p["kernel"] for p in d["passes"]] == ["row", "col", "col"]
+    assert [p["L"] for p in d["passes"]] == [dims[2], dims[1], dims[0]]
+    assert [(p["src"], p["dst"]) for p in d["passes"]] == [(0, 1), (1, 1), (1, 1)]
+    assert d["passes"][1]["s_in"] == dims[2] and d["passes"][2]["s_in"] == dims[1] * dims[2]
+    for p in d["passes"]:
+        assert p["lds"] <= 160 * 1024
+    assert d["workspace_bytes"] == 0
+    n = dims[0] * dims[1] * dims[2]
+    assert d["buffer_bytes"] == b * n * (4 if prec == "fp16" else 8)
+    assert d["scale_log2"] == sum(p["scale"] for p in d["passes"])
+
+
+@pytest.mark.parametrize("dims,status", [((8, 16, 16), 2), ((4096, 16, 16), 2), ((16, 4096, 16), 2),
+                                         ((16, 16, 32768), 2), ((16, 16, 24), 2)])
+def test_plan_3d_rejects(tc, dims, status):
+    with pytest.raises(tc.TcfftError) as e:
+        tc.dry_run(dims, 1)
+    assert e.value.status == status
+    with pytest.raises(tc.TcfftError) as e:
+        tc.dry_run((64, 64, 64), 1, precision="fp32")
     assert e.value.status == 2
