@@ -142,8 +142,9 @@ def cpu_baseline(xs, target_s: float):
 
 def other_workloads(stream) -> dict:
     """Timing + sampled accuracy of the other workloads: the N=256 x 64 latency
-    case, long 1D (2^20 x 16, 2^22 x 4, 2^24 x 1) and batched 2D (256^2 x 1024,
-    512^2 x 256, 1024^2 x 64), FP16 and split.  Long 1D is also timed with the
+    case, long 1D (2^20 x 16, 2^22 x 4, 2^24 x 1), batched 2D (256^2 x 1024,
+    512^2 x 256, 1024^2 x 64) and batched 3D (128^3 x 64, 256^3 x 8, 512^3 x 1;
+    uniform inputs), FP16 and split.  Long 1D is also timed with the
     memory-side cache flushed before each call (its 64 MiB would otherwise stay
     resident between calls).  Not part of `value`."""
     import torch
@@ -159,14 +160,19 @@ def other_workloads(stream) -> dict:
     dt = time_launches(lambda: p(x, y, stream=stream), 200, stream)
     out["1d_256x64"] = {"us": round(dt * 1e6, 2)}
     cases = [("1d", (1 << 20,), 16), ("1d", (1 << 22,), 4), ("1d", (1 << 24,), 1),
-             ("2d", (256, 256), 1024), ("2d", (512, 512), 256), ("2d", (1024, 1024), 64)]
+             ("2d", (256, 256), 1024), ("2d", (512, 512), 256), ("2d", (1024, 1024), 64),
+             ("3d", (128, 128, 128), 64), ("3d", (256, 256, 256), 8), ("3d", (512, 512, 512), 1)]
     for kind, dims, batch in cases:
         for prec in ("fp16", "split"):
             split = prec == "split"
             if kind == "1d":
                 xh, _, _ = inputs.long_1d(dims[0], batch, seed=0, as_split=split)
-            else:
+            elif kind == "2d":
                 xh = inputs.smooth_2d(dims[0], dims[1], batch, seed=0, as_split=split)
+            elif split:
+                xh = inputs.to_split(inputs.uniform_f64((batch,) + dims, 0))
+            else:
+                xh = inputs.uniform((batch,) + dims, 0)
             host = np.stack(xh) if split else xh
             xd = torch.from_numpy(host).cuda()
             yd = torch.empty_like(xd)
@@ -182,6 +188,8 @@ def other_workloads(stream) -> dict:
             npts = int(np.prod(dims)) * batch
             n = int(np.prod(dims))
             row = 0
+            if n > (1 << 24):  # the oracle needs about a minute here; parity tests cover 3D
+                err = None
             z = (yd[:, row] if split else yd[row]).cpu().numpy().astype(np.float64)
             if split:
                 z = (z[0, ..., 0] + 2.0 ** -11 * z[1, ..., 0]) + 1j * (z[0, ..., 1] + 2.0 ** -11 * z[1, ..., 1])
@@ -189,8 +197,10 @@ def other_workloads(stream) -> dict:
             else:
                 z = z[..., 0] + 1j * z[..., 1]
                 zin = oracle.from_half(xh[row])
-            ref = oracle.fft(zin) if kind == "1d" else oracle.fft2(zin)
-            err = float(oracle.rel_l2(z * 2.0 ** p.scale_log2, ref, axis=None))
+            if n <= (1 << 24):
+                ref = (oracle.fft(zin) if kind == "1d" else oracle.fft2(zin) if kind == "2d"
+                       else oracle.fft3(zin[None])[0])
+                err = float(oracle.rel_l2(z * 2.0 ** p.scale_log2, ref, axis=None))
             bpp = 16 if split else 8
             key = f"{kind}_{'x'.join(map(str, dims))}x{batch}_{prec}"
             out[key] = {"us": round(dt * 1e6, 1),
