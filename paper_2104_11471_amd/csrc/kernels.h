@@ -29,7 +29,8 @@ struct KParams {
   uint32_t xmask;          // M - 1
   int64_t xdiv;
   // log2 of blocks, q and xdiv (all powers of two)
-  int32_t blocks_log2, q_log2, xdiv_log2, reserved;
+  int32_t blocks_log2, q_log2, xdiv_log2;
+  float r0scale2;          // plane kernel: scale of the column half's radix-R0 stage
 };
 
 // The same struct is read by host code (x86-64) and, in grouped launches, by
@@ -39,13 +40,13 @@ static_assert(sizeof(KParams) == 168, "KParams layout changed: host and device m
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
-enum KernelKind { K_ROW = 0, K_COL = 1, K_BIG = 2 };
+enum KernelKind { K_ROW = 0, K_COL = 1, K_BIG = 2, K_PLANE = 3 };
 
 struct KernelKey {
   int kind;    // KernelKind
   int L;       // transform length handled in LDS
   int R0;      // 1, 2, 4 or 8: radix of the vector-ALU stage
-  int C;       // column kernel: adjacent columns per workgroup (0 for row)
+  int C;       // column kernel: adjacent columns per workgroup (0 for row); plane: ny
   int NT;      // threads per workgroup
   int split;   // 0 FP16, 1 split hi+lo
   int xtw;     // column kernel: apply the extra inter-pass twiddle
@@ -80,6 +81,7 @@ bool find_col_kernels_256(const KernelKey& key, KernelFns* out);
 bool find_col_kernels_large(const KernelKey& key, KernelFns* out);
 bool find_big_kernels(const KernelKey& key, KernelFns* out);
 bool find_real_row_kernels(const KernelKey& key, KernelFns* out);
+bool find_plane_kernels(const KernelKey& key, KernelFns* out);
 // Returns the single-launch kernel for `key`, or nullptr.
 KernelFn find_kernel(const KernelKey& key);
 // Dynamic LDS bytes the kernel needs.

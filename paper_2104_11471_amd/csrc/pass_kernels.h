@@ -790,12 +790,13 @@ __device__ __forceinline__ void real_pre(const KParams& kp, uint32_t* lds, int v
 }
 
 // One workgroup's share of a row pass: workgroup index wg of the pass.
-// RK: 0 complex; 1 real forward (spectrum epilogue); 2 real inverse (prologue).
+// RK: 0 complex; 1 real forward (spectrum epilogue); 2 real inverse (prologue);
+// 3 results stay in LDS in natural order (the first half of a plane pass).
 template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
 __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = RowGeom<L, R0, NT>;
-  static_assert(RK == 0 || (!TT && G::S >= 1 && L >= 64), "real variants");
-  constexpr bool KEEP = RK == 1, SRCL = RK == 2;
+  static_assert(RK == 0 || (!TT && G::S >= 1 && L >= 64), "real / plane variants");
+  constexpr bool KEEP = RK == 1 || RK == 3, SRCL = RK == 2;
   const int64_t t0 = wg * G::TPB;
   const int64_t rem = kp.ntrans - t0;
   const int valid = rem < G::TPB ? (int)rem : G::TPB;
@@ -821,7 +822,7 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
       row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
     }
   }
-  if constexpr (KEEP) {
+  if constexpr (RK == 1) {
     __syncthreads();
     real_post<G, SPLIT>(kp, lds, valid, t0);
   }
@@ -905,7 +906,9 @@ struct ColCtx {
   int64_t outer;
 };
 
-template <class G, bool SPLIT>
+// SRCL: the block is already in LDS (position j*C + c), read and rewritten in
+// place by the same lane.
+template <class G, bool SPLIT, bool SRCL = false>
 __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, const ColCtx& cx) {
   constexpr int L = G::L, R0 = G::R0, C = G::C, P0 = G::P0;
   uint32_t* ldsl = lds + G::PTS;
@@ -920,10 +923,16 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
     u4 hh[R0], ll[R0];
 #pragma unroll
     for (int d = 0; d < R0; ++d) {
-      const int64_t a = cx.in_base + (int64_t)(d * P0 + lo) * kp.s_in + c;
-      hh[d] = gld4(kp.in + a);
-      if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + a);
-      else ll[d] = u4{0, 0, 0, 0};
+      if constexpr (SRCL) {
+        hh[d] = lds_ld4(lds, (d * P0 + lo) * C + c);
+        if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, (d * P0 + lo) * C + c);
+        else ll[d] = u4{0, 0, 0, 0};
+      } else {
+        const int64_t a = cx.in_base + (int64_t)(d * P0 + lo) * kp.s_in + c;
+        hh[d] = gld4(kp.in + a);
+        if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + a);
+        else ll[d] = u4{0, 0, 0, 0};
+      }
     }
     float2 wt[R0];
 #pragma unroll

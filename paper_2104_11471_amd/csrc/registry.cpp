@@ -6,7 +6,7 @@ namespace tcfft {
 bool find_kernels(const KernelKey& k, KernelFns* out) {
   return find_row_kernels(k, out) || find_col_kernels_small(k, out) ||
          find_col_kernels_256(k, out) || find_col_kernels_large(k, out) ||
-         find_big_kernels(k, out) || find_real_row_kernels(k, out);
+         find_big_kernels(k, out) || find_real_row_kernels(k, out) || find_plane_kernels(k, out);
 }
 
 KernelFn find_kernel(const KernelKey& k) {
@@ -22,6 +22,7 @@ size_t kernel_lds_bytes(const KernelKey& k) {
 
 int64_t kernel_points_per_wg(const KernelKey& k) {
   if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
+  if (k.kind == K_PLANE) return 16384;
   if (k.kind == K_BIG) return k.L;
   return (int64_t)k.L * k.C;
 }

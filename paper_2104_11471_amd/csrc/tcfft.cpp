@@ -83,7 +83,8 @@ struct Choice {
   int chunk = 0;     // multi-pass plans: transforms per chunk (0 = whole batch); all passes
                      // of a chunk run before the next chunk, reusing one workspace region
   int p2row = 0;     // two-pass 1D: pass 1 stores in natural order and pass 2 is a row
-                     // pass over contiguous lines with a transposed store
+                     // pass over contiguous lines with a transposed store.  3D: 1 keeps
+                     // separate row and column passes where a plane pass exists
 };
 
 struct PlanSpec {
@@ -152,6 +153,26 @@ tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst, 
   p.src = src;
   p.dst = dst;
   p.scale = pass_scale(L);
+  ps.passes.push_back(p);
+  return TCFFT_OK;
+}
+
+// Plane pass of a 3D transform: the 2D DFT of each [ny][nz] plane (ny nz =
+// 16384) in one workgroup; `lines` = planes x ny.
+tcfft_status add_plane_pass(PlanSpec& ps, int nz, int ny, int64_t lines) {
+  PassSpec p;
+  p.key = KernelKey{K_PLANE, nz, r0_of(nz), ny, 256, ps.d.prec == TCFFT_PREC_SPLIT_FP16 ? 1 : 0,
+                    0, 0};
+  if ((int64_t)nz * ny != 16384 || nz < 64 || !find_kernel(p.key)) return TCFFT_ERR_UNSUPPORTED;
+  p.tpb = ny;
+  p.ntrans = lines;
+  p.lines_per_batch = lines / ps.d.batch;
+  p.grid = lines / ny;
+  p.s_out = nz;
+  p.lds = kernel_lds_bytes(p.key);
+  p.src = 0;
+  p.dst = 1;
+  p.scale = pass_scale(nz) + pass_scale(ny);
   ps.passes.push_back(p);
   return TCFFT_OK;
 }
@@ -372,9 +393,14 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     // transforms over the B*nx planes [ny][nz], then nx-point transforms over
     // the B blocks [nx][ny*nz]; the column passes run in place in the output
     const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
-    st = add_row_pass(ps, (int)nz, B * nx * ny, 0, 1);
-    if (!st)
-      st = add_col_pass(ps, (int)ny, nz, B * nx, ny * nz, ny * nz, nz, nz, 0, false, 0, 1, 1, 1);
+    // a plane of 16384 points fits one workgroup: rows and columns of the
+    // plane in one pass (the data cross HBM twice instead of three times)
+    const bool plane = !ch.p2row && add_plane_pass(ps, (int)nz, (int)ny, B * nx * ny) == TCFFT_OK;
+    if (!plane) {
+      st = add_row_pass(ps, (int)nz, B * nx * ny, 0, 1);
+      if (!st)
+        st = add_col_pass(ps, (int)ny, nz, B * nx, ny * nz, ny * nz, nz, nz, 0, false, 0, 1, 1, 1);
+    }
     if (!st)
       st = add_col_pass(ps, (int)nx, ny * nz, B, ps.npts, ps.npts, ny * nz, ny * nz, 0, false, 0, 1,
                         1, 1);
@@ -433,7 +459,10 @@ std::string describe(const PlanSpec& ps) {
                   "%s{\"kernel\":\"%s\",\"L\":%d,\"radices\":%s,\"C\":%d,\"NT\":%d,\"grid\":%lld,"
                   "\"lds\":%zu,\"xtw\":%d,\"tstore\":%d,\"scale\":%d,\"src\":%d,\"dst\":%d,"
                   "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld,\"real\":%d}",
-                  i ? "," : "", p.key.kind == K_ROW ? "row" : (p.key.kind == K_BIG ? "big" : "col"),
+                  i ? "," : "",
+                  p.key.kind == K_ROW ? "row"
+                  : p.key.kind == K_BIG ? "big"
+                  : p.key.kind == K_PLANE ? "plane" : "col",
                   p.key.L, rad.c_str(), p.key.C,
                   p.key.NT, (long long)p.grid, p.lds, p.key.xtw, p.key.tstore, p.scale, p.src,
                   p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod, p.key.real);
@@ -587,6 +616,11 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
       launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
+      if (sp.key.kind == K_PLANE) {  // W_ny for the plane's column half
+        if ((st = dev_alloc(p, (size_t)sp.key.C * sizeof(float2), &t))) break;
+        dpp.xtw_lo = (float2*)t;
+        launch_gen_twiddles(dpp.xtw_lo, sp.key.C, sp.key.C, 1, sgn, s);
+      }
       if (sp.key.kind == K_BIG) {  // W_4096 for the 4096-point sub-transforms
         if ((st = dev_alloc(p, 4096 * sizeof(float2), &t))) break;
         dpp.xtw_hi = (float2*)t;
@@ -654,7 +688,12 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.tw = dpp.tw;
   kp.fimg = p->fimg;
   kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
-  if (ps.d.flags & TCFFT_FLAG_NO_SCALE) kp.r0scale = 1.0f;
+  kp.r0scale2 = 1.0f;
+  if (sp.key.kind == K_PLANE) {  // rows of nz, then columns of ny, each with its own radix-R0 scale
+    kp.r0scale = (float)std::ldexp(1.0, -(pass_scale(sp.key.L) - 2 * s16_of(sp.key.L)));
+    kp.r0scale2 = (float)std::ldexp(1.0, -(pass_scale(sp.key.C) - 2 * s16_of(sp.key.C)));
+  }
+  if (ps.d.flags & TCFFT_FLAG_NO_SCALE) kp.r0scale = kp.r0scale2 = 1.0f;
   kp.sgn = (float)ps.d.dir;
   kp.s_in = sp.s_in;
   kp.s_out = sp.s_out;
@@ -1066,14 +1105,18 @@ std::vector<Choice> candidates_base(const Desc& d) {
   if (d.prec == TCFFT_PREC_FP32_RADIX2) return out;
   const bool longp = d.rank == 1 && d.nx > kMaxRowL;
   if (!longp) {
-    for (int nt : {256, 512})
-      for (int cmax : {64, 32, 16, 8}) {
-        if (d.rank == 1 && cmax != 64) continue;
-        Choice c;
-        c.row_nt = nt;
-        c.cmax = cmax;
-        out.push_back(c);
-      }
+    for (int sep : {0, 1}) {
+      if (sep && (d.rank != 3 || d.ny * d.nz != 16384)) continue;  // 3D: also without the plane pass
+      for (int nt : {256, 512})
+        for (int cmax : {64, 32, 16, 8}) {
+          if (d.rank == 1 && cmax != 64) continue;
+          Choice c;
+          c.row_nt = nt;
+          c.cmax = cmax;
+          c.p2row = sep;
+          out.push_back(c);
+        }
+    }
     return out;
   }
   const int lg = ilog2(d.nx);

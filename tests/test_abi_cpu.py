@@ -202,16 +202,26 @@ def test_real_plan_rejects(tc, dims, prec):
 
 @pytest.mark.parametrize("prec", ["fp16", "split"])
 @pytest.mark.parametrize("dims", [(16, 16, 16), (64, 64, 64), (128, 32, 256), (2048, 16, 16),
-                                  (16, 2048, 16384)])
+                                  (16, 2048, 16384), (128, 128, 128), (16, 256, 64),
+                                  (32, 64, 256), (16, 32, 512), (2048, 16, 1024), (16, 512, 32)])
 def test_plan_3d(tc, dims, prec):
-    """A row pass over nz, then column passes over ny and nx, in place in the output."""
+    """A plane pass (ny nz = 16384, nz >= 64: both in one workgroup) or a row
+    pass over nz and a column pass over ny; then a column pass over nx, in
+    place in the output."""
     b = 2
     d = tc.dry_run(dims, b, precision=prec)
     assert d["dims"] == list(dims)
-    assert [p["kernel"] for p in d["passes"]] == ["row", "col", "col"]
-    assert [p["L"] for p in d["passes"]] == [dims[2], dims[1], dims[0]]
-    assert [(p["src"], p["dst"]) for p in d["passes"]] == [(0, 1), (1, 1), (1, 1)]
-    assert d["passes"][1]["s_in"] == dims[2] and d["passes"][2]["s_in"] == dims[1] * dims[2]
+    if dims[1] * dims[2] == 16384 and dims[2] >= 64:
+        assert [p["kernel"] for p in d["passes"]] == ["plane", "col"]
+        assert [p["L"] for p in d["passes"]] == [dims[2], dims[0]]
+        assert d["passes"][0]["C"] == dims[1] and d["passes"][0]["grid"] == b * dims[0]
+        assert [(p["src"], p["dst"]) for p in d["passes"]] == [(0, 1), (1, 1)]
+    else:
+        assert [p["kernel"] for p in d["passes"]] == ["row", "col", "col"]
+        assert [p["L"] for p in d["passes"]] == [dims[2], dims[1], dims[0]]
+        assert [(p["src"], p["dst"]) for p in d["passes"]] == [(0, 1), (1, 1), (1, 1)]
+        assert d["passes"][1]["s_in"] == dims[2]
+    assert d["passes"][-1]["s_in"] == dims[1] * dims[2]
     for p in d["passes"]:
         assert p["lds"] <= 160 * 1024
     assert d["workspace_bytes"] == 0

@@ -10,8 +10,10 @@ from tests.gpu_util import FP16_TOL, SPLIT_TOL, log, run_plan
 
 pytestmark = pytest.mark.gpu
 
+# the last five have a 16384-point [ny][nz] plane: the plane pass
 SHAPES = [((16, 16, 16), 3), ((64, 64, 64), 2), ((128, 32, 256), 1), ((32, 256, 16), 5),
-          ((16, 2048, 32), 1), ((2048, 16, 16), 2)]
+          ((16, 2048, 32), 1), ((2048, 16, 16), 2), ((64, 128, 128), 1), ((16, 256, 64), 3),
+          ((32, 64, 256), 2), ((16, 32, 512), 2), ((16, 16, 1024), 3)]
 
 
 @pytest.fixture(scope="module")
@@ -44,8 +46,9 @@ def test_3d_parity(tc, dims, batch, prec):
         assert e.max() <= tol
 
 
-def test_3d_tuned_and_inplace(tc):
-    dims, batch = (64, 32, 128), 4
+@pytest.mark.parametrize("dims", [(64, 32, 128), (32, 128, 128)])
+def test_3d_tuned_and_inplace(tc, dims):
+    batch = 4
     x = inputs.uniform((batch,) + dims, 32)
     p = tc.Plan(dims, batch, flags=tc.FLAG_TUNE)
     assert p.describe()["tuned"]
@@ -53,10 +56,11 @@ def test_3d_tuned_and_inplace(tc):
     assert rel3(y, oracle.fft3(oracle.from_half(x))).max() <= FP16_TOL
 
 
-def test_3d_plane_wave(tc):
+@pytest.mark.parametrize("shape", [(32, 16, 64), (16, 128, 128)])
+def test_3d_plane_wave(tc, shape):
     """A unit plane wave goes to one bin of height nx*ny*nz (closed form)."""
-    nx, ny, nz = 32, 16, 64
-    f = (5, 9, 50)
+    nx, ny, nz = shape
+    f = (5, 9, 50) if nz == 64 else (7, 100, 3)
     gx, gy, gz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
     w = np.exp(2j * np.pi * (f[0] * gx / nx + f[1] * gy / ny + f[2] * gz / nz))
     x = np.stack([w.real, w.imag], -1).astype(np.float16)[None]
@@ -70,7 +74,8 @@ def test_3d_plane_wave(tc):
 def test_3d_grouped_matches_single(tc):
     import torch
     plans = [tc.Plan((64, 64, 64), 2), tc.Plan((16, 128, 32), 3), tc.Plan((256, 256), 4),
-             tc.Plan((32, 32, 32), 1, precision="split")]
+             tc.Plan((32, 32, 32), 1, precision="split"), tc.Plan((16, 128, 128), 2),
+             tc.Plan((16, 64, 256), 1, precision="split")]
     xs = []
     for k, p in enumerate(plans):
         t = torch.from_numpy(inputs.uniform(p.in_shape()[:-1] if p.precision == 0 else
