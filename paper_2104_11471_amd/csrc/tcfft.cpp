@@ -83,8 +83,8 @@ struct Choice {
   int chunk = 0;     // multi-pass plans: transforms per chunk (0 = whole batch); all passes
                      // of a chunk run before the next chunk, reusing one workspace region
   int p2row = 0;     // two-pass 1D: pass 1 stores in natural order and pass 2 is a row
-                     // pass over contiguous lines with a transposed store.  3D: 1 keeps
-                     // separate row and column passes where a plane pass exists
+                     // pass over contiguous lines with a transposed store.  2D / 3D: 1
+                     // keeps separate row and column passes where a plane pass exists
 };
 
 struct PlanSpec {
@@ -384,10 +384,13 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     }
   } else if (d.rank == 2) {
     const int64_t nx = d.nx, ny = d.ny;
+    // a 16384-point array fits one workgroup: rows and columns in one pass
+    const bool plane = !ch.p2row && add_plane_pass(ps, (int)ny, (int)nx, B * nx) == TCFFT_OK;
     // rows: B*nx contiguous ny-point transforms; then columns: B blocks of
     // [nx][ny], strided nx-point transforms, in place in the output
-    st = add_row_pass(ps, (int)ny, B * nx, 0, 1);
-    if (!st) st = add_col_pass(ps, (int)nx, ny, B, nx * ny, nx * ny, ny, ny, 0, false, 0, 1, 1, 1);
+    if (!plane) st = add_row_pass(ps, (int)ny, B * nx, 0, 1);
+    if (!plane && !st)
+      st = add_col_pass(ps, (int)nx, ny, B, nx * ny, nx * ny, ny, ny, 0, false, 0, 1, 1, 1);
   } else {
     // the 3D DFT is separable: rows of nz (contiguous), then ny-point
     // transforms over the B*nx planes [ny][nz], then nx-point transforms over
@@ -1106,7 +1109,9 @@ std::vector<Choice> candidates_base(const Desc& d) {
   const bool longp = d.rank == 1 && d.nx > kMaxRowL;
   if (!longp) {
     for (int sep : {0, 1}) {
-      if (sep && (d.rank != 3 || d.ny * d.nz != 16384)) continue;  // 3D: also without the plane pass
+      // with a plane pass possible, also the separate row and column passes
+      if (sep && d.ny * d.nz * (d.rank == 2 ? d.nx : 1) != 16384) continue;
+      if (sep && d.rank == 1) continue;
       for (int nt : {256, 512})
         for (int cmax : {64, 32, 16, 8}) {
           if (d.rank == 1 && cmax != 64) continue;

@@ -86,11 +86,15 @@ def test_plan_factorises_every_1d_size(tc, lg):
 
 @pytest.mark.parametrize("prec", ["fp16", "split"])
 @pytest.mark.parametrize("dims", [(16, 16), (256, 256), (512, 512), (1024, 1024), (2048, 64),
-                                  (128, 16384)])
+                                  (128, 16384), (128, 128), (256, 64), (16, 1024), (512, 32)])
 def test_plan_2d(tc, dims, prec):
     d = tc.dry_run(dims, 2, precision=prec)
-    assert [p["kernel"] for p in d["passes"]] == ["row", "col"]
-    assert d["passes"][0]["L"] == dims[1] and d["passes"][1]["L"] == dims[0]
+    if dims[0] * dims[1] == 16384 and dims[1] >= 64:  # one workgroup per array
+        assert [p["kernel"] for p in d["passes"]] == ["plane"]
+        assert d["passes"][0]["L"] == dims[1] and d["passes"][0]["C"] == dims[0]
+    else:
+        assert [p["kernel"] for p in d["passes"]] == ["row", "col"]
+        assert d["passes"][0]["L"] == dims[1] and d["passes"][1]["L"] == dims[0]
     for p in d["passes"]:
         assert p["lds"] <= 160 * 1024
     assert d["buffer_bytes"] == 2 * dims[0] * dims[1] * (4 if prec == "fp16" else 8)

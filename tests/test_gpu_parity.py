@@ -87,9 +87,13 @@ def test_inverse_and_roundtrip(tc, n):
 
 
 @pytest.mark.parametrize("dims", [(16, 16), (64, 512), (256, 256), (512, 128), (1024, 1024),
-                                  (2048, 16)])
+                                  (2048, 16), (128, 128), (256, 64), (32, 512), (16, 1024)])
 def test_2d(tc, dims):
+    """The last four are 16384-point arrays: one plane pass per array."""
     _check(tc, dims, 3 if dims[0] * dims[1] <= 65536 else 1)
+    if dims[0] * dims[1] == 16384 and dims[1] >= 64:
+        _check(tc, dims, 5, sign=1)
+        _check(tc, dims, 2, prec="split")
 
 
 @pytest.mark.parametrize("dims", [(256,), (4096,), (16384,), (1 << 16,), (1 << 20,), (128, 128),
