@@ -91,7 +91,9 @@ enum {
  * DFT (the rest follow by Hermitian symmetry), M+1 complex words per
  * transform.  FORWARD reads batch*M words and writes batch*(M+1); INVERSE
  * reads batch*(M+1) words (the imaginary parts of X[0] and X[M] are ignored)
- * and writes batch*M words holding N * x * 2^-S.  The plan runs an M-point
+ * and writes batch*M words holding N * x * 2^-S.  Input and output must not
+ * overlap (lines of M and M + 1 words cannot be rewritten in place).  The plan
+ * runs an M-point
  * complex transform plus one elementwise pass (Eq. 2 with a radix-2 split of
  * the real sequence into its even and odd points); split precision stores
  * both buffers as a hi plane then a lo plane.
@@ -113,11 +115,12 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 /*
  * Executes a plan (the "execution function" of Fig. 1): reads `in`, writes
  * `out` (device pointers of tcfft_plan_input_bytes() and
- * tcfft_plan_output_bytes(), 16-byte aligned; in == out allowed when the
- * buffer holds the larger of the two), enqueued asynchronously on `stream` (a
+ * tcfft_plan_output_bytes(), 16-byte aligned; in == out allowed for complex
+ * plans, real plans need disjoint buffers), enqueued asynchronously on `stream` (a
  * hipStream_t or NULL).  One exec per plan may be in flight at a time (the
  * plan's workspace is shared).
- * Errors: INVALID_ARG (null plan/pointer, misalignment), LAUNCH.
+ * Errors: INVALID_ARG (null plan/pointer, misalignment, overlapping buffers of
+ * a real plan), LAUNCH.
  */
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream);
 

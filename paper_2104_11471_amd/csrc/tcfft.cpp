@@ -1308,6 +1308,15 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+// Real plans read lines of M words and write lines of M + 1 (or the reverse):
+// workgroups would overwrite input that others have not read yet, so their
+// input and output must not overlap.
+bool real_overlap(const tcfft_plan_s* p, const void* in, const void* out) {
+  if (p->spec.real_n == 0) return false;
+  const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  return a < b + p->spec.out_bytes && b < a + p->spec.in_bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1345,7 +1354,7 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream) {
   if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
-  if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out) || real_overlap(plan, in, out)) return TCFFT_ERR_INVALID_ARG;
   return exec_any(plan, in, out, (hipStream_t)stream);
 }
 
@@ -1363,7 +1372,8 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
                              int njobs, void* stream) {
   if (njobs < 0 || (njobs > 0 && (!plans || !in || !out))) return TCFFT_ERR_INVALID_ARG;
   for (int j = 0; j < njobs; ++j)
-    if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]))
+    if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]) ||
+        real_overlap(plans[j], in[j], out[j]))
       return TCFFT_ERR_INVALID_ARG;
   if (njobs == 0) return TCFFT_OK;
   try {

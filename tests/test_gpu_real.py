@@ -112,19 +112,15 @@ def test_real_many_lines(tc, n, batch, prec):
 
 @pytest.mark.parametrize("n", [64, 4096, 1 << 20])
 def test_round_trip(tc, n):
-    """C2R(R2C(x)) = N x 2^-(S_f + S_i), on the device in place."""
+    """C2R(R2C(x)) = N x 2^-(S_f + S_i), with many workgroups of lines."""
     import torch
-    b = 3
-    log(f"case real round trip n={n}")
+    b = max(3, (1 << 22) // n)
+    log(f"case real round trip n={n} batch={b}")
     f = tc.Plan((n,), b, tc.FORWARD, "fp16", flags=tc.FLAG_REAL)
     i = tc.Plan((n,), b, tc.INVERSE, "fp16", flags=tc.FLAG_REAL)
     host, val = real_input(n, b, "fp16", 23)
-    buf = torch.zeros(b * (n // 2 + 1) * 2, dtype=torch.float16, device="cuda")
-    buf[: b * n] = torch.from_numpy(host).cuda().reshape(-1)
-    f.exec_raw(buf.data_ptr(), buf.data_ptr(), torch.cuda.current_stream().cuda_stream)
-    i.exec_raw(buf.data_ptr(), buf.data_ptr(), torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
-    y = buf[: b * n].reshape(b, n).cpu().numpy().astype(np.float64)
+    spec = f(torch.from_numpy(host).cuda())
+    y = i(spec).cpu().numpy().astype(np.float64)
     y *= 2.0 ** (f.scale_log2 + i.scale_log2)
     e = oracle.rel_l2(y, n * val)
     log(f"  max rel L2 = {e.max():.3e}")
@@ -160,6 +156,22 @@ def test_real_grouped_matches_single(tc):
     torch.cuda.synchronize()
     for a, o in zip(singles, outs):
         assert torch.equal(a.view(torch.int16), o.view(torch.int16))
+
+
+def test_real_rejects_overlap(tc):
+    """Lines of M and M + 1 words cannot be rewritten in place: overlapping
+    buffers of a real plan are an argument error, nothing is launched."""
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    for dirn in (tc.FORWARD, tc.INVERSE):
+        p = tc.Plan((4096,), 2, dirn, "fp16", flags=tc.FLAG_REAL)
+        buf = torch.empty(2 * 2049 * 2 + 8, dtype=torch.float16, device="cuda")
+        for off in (0, 8):  # the same pointer, and a shifted one
+            st = tc.lib.tcfft_exec(p.handle, buf.data_ptr(), buf.data_ptr() + 2 * off, s)
+            assert st == 1
+        hp = (tc.ctypes.c_void_p * 1)(p.handle)
+        ip = (tc.ctypes.c_void_p * 1)(buf.data_ptr())
+        assert tc.lib.tcfft_exec_many(hp, ip, ip, 1, s) == 1
 
 
 def test_real_describe(tc):
