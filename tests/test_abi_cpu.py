@@ -144,16 +144,24 @@ def test_null_arguments(tc):
 
 
 def test_tune_candidates_are_valid_plans(tc):
-    for dims in [(4096,), (16384,), (65536,), (1 << 20,), (1 << 24,), (256, 256), (1024, 1024)]:
+    for dims in [(4096,), (16384,), (65536,), (1 << 20,), (1 << 24,), (256, 256), (1024, 1024),
+                 (128, 128), (64, 64, 64), (16, 128, 128)]:
         cands = tc.tune_candidates(dims, 8)
         assert len(cands) >= 1
-        n = dims[0] * (dims[1] if len(dims) == 2 else 1)
+        n = 1
+        for v in dims:
+            n *= v
+        kinds = set()
         for d in cands:
             prod = 1
             for p in d["passes"]:
-                prod *= p["L"]
+                # a plane pass covers its nz (L) and ny (C) dimensions
+                prod *= p["L"] * (p["C"] if p["kernel"] == "plane" else 1)
                 assert p["lds"] <= 160 * 1024
+                kinds.add(p["kernel"])
             assert prod == n
+        if len(dims) >= 2 and dims[-1] * dims[-2] == 16384:
+            assert "plane" in kinds and "row" in kinds  # both plans are timed
 
 
 def test_tune_cache_file_errors(tc, tmp_path):
