@@ -87,3 +87,18 @@ def test_3d_grouped_matches_single(tc):
     torch.cuda.synchronize()
     for a, o in zip(singles, outs):
         assert torch.equal(a.view(torch.int16), o.view(torch.int16))
+
+
+@pytest.mark.parametrize("dims", [(128, 128), (16, 128, 128), (32, 64, 256), (16, 16, 16)])
+def test_no_scale_plane_and_3d(tc, dims):
+    """TCFFT_FLAG_NO_SCALE (S = 0) through the plane pass, whose row and column
+    halves each carry their own radix-R0 scale, and through 3D plans; inputs
+    are scaled down so the unnormalised FP16 output stays in range."""
+    batch = 2
+    x = (inputs.uniform((batch,) + dims, 33).astype(np.float32) / 64).astype(np.float16)
+    p = tc.Plan(dims, batch, flags=tc.FLAG_NO_SCALE)
+    assert p.scale_log2 == 0
+    y = run_plan(p, x)
+    ref = oracle.fft2(oracle.from_half(x)) if len(dims) == 2 else oracle.fft3(oracle.from_half(x))
+    axes = (-2, -1) if len(dims) == 2 else (-3, -2, -1)
+    assert oracle.rel_l2(y, ref, axis=axes).max() <= FP16_TOL

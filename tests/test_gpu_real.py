@@ -184,3 +184,19 @@ def test_real_describe(tc):
     assert tc.Plan((1 << 16,), 1, tc.FORWARD, "fp16", flags=tc.FLAG_REAL).num_launches == 3
     x, o = p.empty(), p.empty_out()
     assert tc.lib.tcfft_exec_passes(p.handle, x.data_ptr(), o.data_ptr(), 1, None) == 2
+
+
+@pytest.mark.parametrize("n", [128, 8192, 32768, 65536])
+def test_real_no_scale(tc, n):
+    """Unnormalised real transforms (S = 0), fused and stand-alone steps."""
+    import torch
+    b = 2
+    f = tc.Plan((n,), b, tc.FORWARD, "fp16", flags=tc.FLAG_REAL | tc.FLAG_NO_SCALE)
+    i = tc.Plan((n,), b, tc.INVERSE, "fp16", flags=tc.FLAG_REAL | tc.FLAG_NO_SCALE)
+    assert f.scale_log2 == 0 and i.scale_log2 == 0
+    host = (inputs.uniform((b, n // 2), 26).astype(np.float32) / 256).astype(np.float16).reshape(b, n)
+    spec = f(torch.from_numpy(host).cuda())
+    y = read_spectrum(spec, "fp16")
+    assert oracle.rel_l2(y, oracle.rfft(host.astype(np.float64))).max() <= FP16_TOL
+    back = read_real(i(spec), "fp16")
+    assert oracle.rel_l2(back, n * host.astype(np.float64)).max() <= 2 * FP16_TOL
