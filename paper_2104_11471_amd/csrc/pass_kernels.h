@@ -902,6 +902,7 @@ struct ColGeom {
 
 struct ColCtx {
   int64_t in_base, out_base;  // element offsets of tile column 0
+  int lds_off = 0;            // LDS position of the block (several blocks per workgroup)
   int64_t i0;                 // first global column index of the tile
   int64_t outer;
 };
@@ -924,8 +925,8 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
 #pragma unroll
     for (int d = 0; d < R0; ++d) {
       if constexpr (SRCL) {
-        hh[d] = lds_ld4(lds, (d * P0 + lo) * C + c);
-        if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, (d * P0 + lo) * C + c);
+        hh[d] = lds_ld4(lds, cx.lds_off + (d * P0 + lo) * C + c);
+        if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, cx.lds_off + (d * P0 + lo) * C + c);
         else ll[d] = u4{0, 0, 0, 0};
       } else {
         const int64_t a = cx.in_base + (int64_t)(d * P0 + lo) * kp.s_in + c;
@@ -958,7 +959,7 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
         h[t] = eh;
         l[t] = el;
       }
-      const int p = (k * P0 + lo) * C + c;
+      const int p = cx.lds_off + (k * P0 + lo) * C + c;
       lds_st4(lds, p, h);
       if constexpr (SPLIT) lds_st4(ldsl, p, l);
     }
@@ -1007,8 +1008,8 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
         rh[i] = gld4(kp.in + a);
         if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + a);
       } else {
-        rh[i] = lds_ld4(lds, j * C + c);
-        if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, j * C + c);
+        rh[i] = lds_ld4(lds, cx.lds_off + j * C + c);
+        if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, cx.lds_off + j * C + c);
       }
       if constexpr (!SPLIT) rl[i] = u4{0, 0, 0, 0};
     }
@@ -1067,7 +1068,7 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
       if (active) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = (jb + (4 * g + j) * P) * C + c;
+          const int p = cx.lds_off + (jb + (4 * g + j) * P) * C + c;
           lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
           if constexpr (SPLIT) lds_st4(ldsl, p, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
         }

@@ -157,17 +157,20 @@ tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst, 
   return TCFFT_OK;
 }
 
-// Plane pass of a 3D transform: the 2D DFT of each [ny][nz] plane (ny nz =
-// 16384) in one workgroup; `lines` = planes x ny.
+// Plane pass of a 3D transform: the 2D DFT of [ny][nz] planes in one
+// workgroup, 16384 points per workgroup (one plane, or 2 or 4 planes of 8192 or
+// 4096 points in FP16); `lines` = planes x ny.
 tcfft_status add_plane_pass(PlanSpec& ps, int nz, int ny, int64_t lines) {
   PassSpec p;
   p.key = KernelKey{K_PLANE, nz, r0_of(nz), ny, 256, ps.d.prec == TCFFT_PREC_SPLIT_FP16 ? 1 : 0,
                     0, 0};
-  if ((int64_t)nz * ny != 16384 || nz < 64 || !find_kernel(p.key)) return TCFFT_ERR_UNSUPPORTED;
-  p.tpb = ny;
+  const int64_t pl = (int64_t)nz * ny;
+  if ((pl != 16384 && pl != 8192 && pl != 4096) || nz < 64 || !find_kernel(p.key))
+    return TCFFT_ERR_UNSUPPORTED;
+  p.tpb = 16384 / nz;  // lines per workgroup: whole planes
   p.ntrans = lines;
   p.lines_per_batch = lines / ps.d.batch;
-  p.grid = lines / ny;
+  p.grid = (lines + p.tpb - 1) / p.tpb;
   p.s_out = nz;
   p.lds = kernel_lds_bytes(p.key);
   p.src = 0;
@@ -1110,8 +1113,9 @@ std::vector<Choice> candidates_base(const Desc& d) {
   if (!longp) {
     for (int sep : {0, 1}) {
       // with a plane pass possible, also the separate row and column passes
-      if (sep && d.ny * d.nz * (d.rank == 2 ? d.nx : 1) != 16384) continue;
-      if (sep && d.rank == 1) continue;
+      const int64_t plane_pts = d.rank == 2 ? d.nx * d.ny : d.ny * d.nz;
+      if (sep && (d.rank == 1 || (plane_pts != 16384 && plane_pts != 8192 && plane_pts != 4096)))
+        continue;
       for (int nt : {256, 512})
         for (int cmax : {64, 32, 16, 8}) {
           if (d.rank == 1 && cmax != 64) continue;

@@ -84,12 +84,18 @@ def test_plan_factorises_every_1d_size(tc, lg):
     assert len(d["passes"]) == (1 if n <= 16384 else (2 if n <= (1 << 22) else 3))
 
 
+def plane_plan(pts, nz, prec):
+    """16384 points per workgroup: one plane, or (FP16) 2 or 4 smaller ones."""
+    return nz >= 64 and (pts == 16384 or (prec == "fp16" and pts in (4096, 8192)))
+
+
 @pytest.mark.parametrize("prec", ["fp16", "split"])
 @pytest.mark.parametrize("dims", [(16, 16), (256, 256), (512, 512), (1024, 1024), (2048, 64),
-                                  (128, 16384), (128, 128), (256, 64), (16, 1024), (512, 32)])
+                                  (128, 16384), (128, 128), (256, 64), (16, 1024), (512, 32),
+                                  (64, 64), (32, 128), (64, 128), (128, 64), (32, 256), (16, 64)])
 def test_plan_2d(tc, dims, prec):
     d = tc.dry_run(dims, 2, precision=prec)
-    if dims[0] * dims[1] == 16384 and dims[1] >= 64:  # one workgroup per array
+    if plane_plan(dims[0] * dims[1], dims[1], prec):  # one workgroup per 16384 points
         assert [p["kernel"] for p in d["passes"]] == ["plane"]
         assert d["passes"][0]["L"] == dims[1] and d["passes"][0]["C"] == dims[0]
     else:
@@ -215,7 +221,9 @@ def test_real_plan_rejects(tc, dims, prec):
 @pytest.mark.parametrize("prec", ["fp16", "split"])
 @pytest.mark.parametrize("dims", [(16, 16, 16), (64, 64, 64), (128, 32, 256), (2048, 16, 16),
                                   (16, 2048, 16384), (128, 128, 128), (16, 256, 64),
-                                  (32, 64, 256), (16, 32, 512), (2048, 16, 1024), (16, 512, 32)])
+                                  (32, 64, 256), (16, 32, 512), (2048, 16, 1024), (16, 512, 32),
+                                  (64, 64, 64), (16, 32, 128), (16, 128, 64), (32, 64, 128),
+                                  (16, 32, 256)])
 def test_plan_3d(tc, dims, prec):
     """A plane pass (ny nz = 16384, nz >= 64: both in one workgroup) or a row
     pass over nz and a column pass over ny; then a column pass over nx, in
@@ -223,10 +231,11 @@ def test_plan_3d(tc, dims, prec):
     b = 2
     d = tc.dry_run(dims, b, precision=prec)
     assert d["dims"] == list(dims)
-    if dims[1] * dims[2] == 16384 and dims[2] >= 64:
+    if plane_plan(dims[1] * dims[2], dims[2], prec):
         assert [p["kernel"] for p in d["passes"]] == ["plane", "col"]
         assert [p["L"] for p in d["passes"]] == [dims[2], dims[0]]
-        assert d["passes"][0]["C"] == dims[1] and d["passes"][0]["grid"] == b * dims[0]
+        npl = 16384 // (dims[1] * dims[2])  # planes per workgroup
+        assert d["passes"][0]["C"] == dims[1] and d["passes"][0]["grid"] == -(-b * dims[0] // npl)
         assert [(p["src"], p["dst"]) for p in d["passes"]] == [(0, 1), (1, 1)]
     else:
         assert [p["kernel"] for p in d["passes"]] == ["row", "col", "col"]

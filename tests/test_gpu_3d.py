@@ -10,10 +10,14 @@ from tests.gpu_util import FP16_TOL, SPLIT_TOL, log, run_plan
 
 pytestmark = pytest.mark.gpu
 
-# the last five have a 16384-point [ny][nz] plane: the plane pass
+# from (64, 128, 128) on: [ny][nz] planes of 16384 points (plane pass); the
+# 4096- and 8192-point planes take the plane pass in FP16 only
 SHAPES = [((16, 16, 16), 3), ((64, 64, 64), 2), ((128, 32, 256), 1), ((32, 256, 16), 5),
           ((16, 2048, 32), 1), ((2048, 16, 16), 2), ((64, 128, 128), 1), ((16, 256, 64), 3),
-          ((32, 64, 256), 2), ((16, 32, 512), 2), ((16, 16, 1024), 3)]
+          ((32, 64, 256), 2), ((16, 32, 512), 2), ((16, 16, 1024), 3),
+          # FP16: 4 planes of 4096 or 2 of 8192 points per workgroup
+          ((16, 64, 64), 3), ((16, 32, 128), 2), ((32, 128, 64), 1), ((16, 64, 128), 2),
+          ((16, 32, 256), 1)]
 
 
 @pytest.fixture(scope="module")

@@ -87,10 +87,16 @@ def test_inverse_and_roundtrip(tc, n):
 
 
 @pytest.mark.parametrize("dims", [(16, 16), (64, 512), (256, 256), (512, 128), (1024, 1024),
-                                  (2048, 16), (128, 128), (256, 64), (32, 512), (16, 1024)])
+                                  (2048, 16), (128, 128), (256, 64), (32, 512), (16, 1024),
+                                  (64, 64), (32, 128), (128, 64), (64, 128), (32, 256)])
 def test_2d(tc, dims):
-    """The last four are 16384-point arrays: one plane pass per array."""
+    """From (128, 128) on: arrays of 16384 points (one plane pass per array)
+    and, in FP16, of 4096 / 8192 points (4 / 2 arrays per workgroup; batches of
+    3, 5 and 7 end inside a workgroup)."""
     _check(tc, dims, 3 if dims[0] * dims[1] <= 65536 else 1)
+    if dims[0] * dims[1] < 16384:
+        _check(tc, dims, 5)
+        _check(tc, dims, 7, sign=1)
     if dims[0] * dims[1] == 16384 and dims[1] >= 64:
         _check(tc, dims, 5, sign=1)
         _check(tc, dims, 2, prec="split")
