@@ -635,16 +635,19 @@ __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds
 // line = it / NQ, else j = t mod M/2 and line = t / (M/2) + it NT / (M/2): the
 // line and the high part of j are compile-time per item, and the twiddle
 // W^j = W^t * W^{NT q} is one table load per thread times a uniform value.
-// Items go U per thread with every load of a group issued before its first use.
+// Items go in groups per thread with every load of a group issued before its
+// first use: 32 items per group for the epilogue (LDS loads), 16 for the
+// prologue (HBM loads; larger groups measured slower there).
 template <class G>
 struct RealLoop {
   static constexpr int M = G::L, HM = M / 2, NT = G::NT;
   static constexpr int ITER = G::TPB * HM / NT;
-  static constexpr int U = ITER < 8 ? ITER : 8;
+  static constexpr int UPOST = ITER < 32 ? ITER : 32, UPRE = ITER < 16 ? ITER : 16;
   static constexpr bool WIDE = HM >= NT;       // a line spans NQ items of a thread
   static constexpr int NQ = WIDE ? HM / NT : 1;
   static constexpr int LPI = WIDE ? 1 : NT / HM;  // lines per item step
-  static_assert(ITER >= 1 && ITER * NT == G::TPB * HM && ITER % U == 0, "item split");
+  static_assert(ITER >= 1 && ITER * NT == G::TPB * HM && ITER % UPOST == 0 && ITER % UPRE == 0,
+                "item split");
   __device__ static int line(int it) {
     return WIDE ? it / NQ : (int)threadIdx.x / HM + it * LPI;
   }
@@ -692,7 +695,7 @@ template <class G, bool SPLIT>
 __device__ __forceinline__ void real_post(const KParams& kp, const uint32_t* lds, int valid,
                                           int64_t t0) {
   using R = RealLoop<G>;
-  constexpr int M = R::M, HM = R::HM, U = R::U;
+  constexpr int M = R::M, HM = R::HM, U = R::UPOST;
   const uint32_t* ldsl = lds + G::PTS;
   uint32_t* const oh = kp.out + t0 * (int64_t)(M + 1);
   uint32_t* const ol = oh + kp.out_plane;
@@ -740,7 +743,7 @@ __device__ __forceinline__ void real_post(const KParams& kp, const uint32_t* lds
 template <class G, bool SPLIT>
 __device__ __forceinline__ void real_pre(const KParams& kp, uint32_t* lds, int valid, int64_t t0) {
   using R = RealLoop<G>;
-  constexpr int M = R::M, HM = R::HM, U = R::U;
+  constexpr int M = R::M, HM = R::HM, U = R::UPRE;
   uint32_t* ldsl = lds + G::PTS;
   const uint32_t* const xh = kp.in + t0 * (int64_t)(M + 1);
   const uint32_t* const xl = xh + kp.in_plane;
@@ -1309,8 +1312,11 @@ __device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
 // FP16 row tiles use 64 KB of LDS, so two workgroups share a CU: the register
 // budget is capped to match (the persistent loop otherwise keeps enough
 // loop-invariant addresses live to drop to one workgroup per CU).
+// (the real-input variants carry their epilogue / prologue through the
+// persistent loop: one workgroup per CU keeps them out of scratch)
 template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
-__global__ __launch_bounds__(NT, SPLIT ? 1 : 2) void row_kernel_multi(const GroupHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(NT, (SPLIT || RK != 0) ? 1 : 2) void row_kernel_multi(
+    const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
   CGroupHdr* h = (CGroupHdr*)hdr;
   CKParams* jobs = (CKParams*)h->jobs;
