@@ -79,7 +79,8 @@ def test_3d_grouped_matches_single(tc):
     import torch
     plans = [tc.Plan((64, 64, 64), 2), tc.Plan((16, 128, 32), 3), tc.Plan((256, 256), 4),
              tc.Plan((32, 32, 32), 1, precision="split"), tc.Plan((16, 128, 128), 2),
-             tc.Plan((16, 64, 256), 1, precision="split")]
+             tc.Plan((16, 64, 256), 1, precision="split"), tc.Plan((64, 64), 7),
+             tc.Plan((16, 32, 128), 3)]
     xs = []
     for k, p in enumerate(plans):
         t = torch.from_numpy(inputs.uniform(p.in_shape()[:-1] if p.precision == 0 else
