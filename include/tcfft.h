@@ -132,9 +132,13 @@ tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream
  * device-resident descriptor table lists the jobs and their workgroup
  * ranges), so a batch of hundreds of uneven transforms costs a handful of
  * launches.  Each job's result is bitwise equal to tcfft_exec of that job
- * alone.  Jobs must not share a plan (workspace) or an output buffer.
- * Errors: as tcfft_exec; INVALID_ARG for njobs < 0 or null arrays; ALLOC
- * when the descriptor table cannot be allocated (stream-ordered).
+ * alone.  Jobs must not share an output buffer.  A plan that holds a
+ * workspace (multi-pass plans; real plans whose spectrum step is a separate
+ * pass) may appear in only one job of a call, since its jobs would write the
+ * same intermediate; single-pass plans may repeat.
+ * Errors: as tcfft_exec; INVALID_ARG for njobs < 0, null arrays or a
+ * workspace-holding plan listed twice; ALLOC when the descriptor table cannot
+ * be allocated (stream-ordered).
  */
 tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
                              int njobs, void* stream);

@@ -1312,6 +1312,11 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+// Whether exec writes plan-owned intermediate memory (workspace or spectrum buffer).
+bool plan_has_scratch(const tcfft_plan_s* p) {
+  return p->spec.ws_bytes > 0 || p->spec.zbuf_bytes > 0;
+}
+
 // Real plans read lines of M words and write lines of M + 1 (or the reverse):
 // workgroups would overwrite input that others have not read yet, so their
 // input and output must not overlap.
@@ -1379,6 +1384,14 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
     if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]) ||
         real_overlap(plans[j], in[j], out[j]))
       return TCFFT_ERR_INVALID_ARG;
+  // a plan with a workspace (multi-pass) or a spectrum buffer (real plans
+  // with a separate spectrum pass) can serve only one job of a grouped launch:
+  // two jobs would write the same intermediate inside one launch
+  for (int j = 0; j < njobs; ++j) {
+    if (!plan_has_scratch(plans[j])) continue;
+    for (int i = 0; i < j; ++i)
+      if (plans[i] == plans[j]) return TCFFT_ERR_INVALID_ARG;
+  }
   if (njobs == 0) return TCFFT_OK;
   try {
     return exec_many_impl(plans, in, out, njobs, (hipStream_t)stream);

@@ -118,3 +118,24 @@ def test_chunked_execution_is_bitwise_equal(dims, batch, chunk, tmp_path):
     torch.cuda.synchronize()
     assert torch.equal(y.view(torch.int16), whole.view(torch.int16))
     tcfft.tune_cache_clear()
+
+
+def test_exec_many_rejects_a_workspace_plan_twice():
+    """Two jobs of one multi-pass plan would write the plan's workspace inside
+    one grouped launch: the call is rejected; single-pass plans may repeat."""
+    import torch
+    from paper_2104_11471_amd import tcfft
+    p = tcfft.Plan((1 << 17,), 1)
+    assert p.workspace_bytes > 0
+    xs = [torch.from_numpy(inputs.uniform((1, 1 << 17), 30 + k)).cuda() for k in range(2)]
+    outs = [torch.empty_like(x) for x in xs]
+    with pytest.raises(tcfft.TcfftError) as ei:
+        tcfft.exec_many([p, p], xs, outs)
+    assert ei.value.status == 1
+    q = tcfft.Plan((1024,), 4)
+    assert q.workspace_bytes == 0
+    ys = [torch.from_numpy(inputs.uniform((4, 1024), 40 + k)).cuda() for k in range(3)]
+    many = [torch.empty_like(y) for y in ys]
+    tcfft.exec_many([q, q, q], ys, many)
+    for y, m in zip(ys, many):
+        assert torch.equal(q(y).view(torch.int16), m.view(torch.int16))
