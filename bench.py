@@ -307,6 +307,45 @@ def serving_leg(seconds: float) -> dict:
     return main
 
 
+def parse_run_spec(spec: str):
+    """'1d:16384:8192:fp16' | '2d:256x256:1024:split' | '3d:128x128x128:64:fp16'
+    -> (kind, dims, batch, precision)."""
+    kind, dims, batch, prec = spec.split(":")
+    return kind, tuple(int(v) for v in dims.split("x")), int(batch), prec
+
+
+def run_workloads(specs, reps: int, stream) -> dict:
+    """Profiling mode: plans (autotuned, or from a loaded cache) of the listed
+    workloads, each executed `reps` times back to back after one warm-up,
+    with the HIP-event mean per execution.  Inputs are seeded uniform values."""
+    import torch
+    from paper_2104_11471_amd import inputs, tcfft
+    out = {}
+    for spec in specs:
+        kind, dims, batch, prec = parse_run_spec(spec)
+        log(f"run {spec}")
+        split = prec == "split"
+        shape = (batch,) + dims
+        host = (np.stack(inputs.to_split(inputs.uniform_f64(shape, 0))) if split
+                else inputs.uniform(shape, 0))
+        xd = torch.from_numpy(host).cuda()
+        yd = torch.empty_like(xd)
+        p = tcfft.Plan(dims, batch, precision=prec, flags=tcfft.FLAG_TUNE)
+        torch.cuda.synchronize()
+        p(xd, yd, stream=stream)
+        dt = time_launches(lambda: p(xd, yd, stream=stream), reps, stream)
+        d = p.describe()
+        npts = int(np.prod(dims)) * batch
+        bpp = 16 if split else 8
+        out[spec] = {"us": round(dt * 1e6, 2), "hbm_frac_alg": round(bpp * npts / dt / 1e12 / 8.0, 4),
+                     "choice": d["choice"],
+                     "passes": [(q["kernel"], q["L"], q["C"], q["NT"], q["grid"]) for q in d["passes"]]}
+        log(f"  {out[spec]}")
+        del xd, yd, p
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +364,10 @@ def main():
     ap.add_argument("--save-wisdom", default="", help="save the autotuner cache after planning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--run", default="",
+                    help="profiling mode: comma-separated workloads kind:dims:batch:precision "
+                         "(e.g. 1d:16384:8192:fp16,2d:256x256:1024:split), each run --reps times")
+    ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
     global SIZES
     if args.only:
@@ -349,6 +392,12 @@ def main():
         return
     if args.wisdom:
         tcfft.tune_cache_load(args.wisdom)
+    if args.run:
+        res = run_workloads(args.run.split(","), args.reps, stream)
+        if args.save_wisdom:
+            tcfft.tune_cache_save(args.save_wisdom)
+        print(json.dumps({"run": res}), flush=True)
+        return
     plans, xs, xd, yd = {}, {}, {}, {}
     for n in SIZES:
         batch = TOTAL_POINTS // n
