@@ -89,6 +89,27 @@ def measured_traffic(kernel_name: str):
     return int(round((k["fetch"] * rec["fetch_factor"] + k["write"] * rec["write_factor"]) * 1024))
 
 
+def kernel_name(q: dict) -> str:
+    """Template name of a pass's kernel from the plan description."""
+    r0 = q["radices"][0] if q["radices"][0] != 16 else 1
+    if q["kernel"] == "row":
+        return f"row_kernel<{q['L']}, {r0}, {q['NT']}, false, {str(bool(q['tstore'])).lower()}, {q['real']}>"
+    if q["kernel"] == "col":
+        return (f"col_kernel<{q['L']}, {r0}, {q['C']}, {q['NT']}, false, "
+                f"{str(bool(q['xtw'])).lower()}, {str(bool(q['tstore'])).lower()}>")
+    return f"{q['kernel']}_kernel<{q['L']}>"
+
+
+def pass_times(plan, x, y, stream, reps: int = 10) -> list:
+    """HIP-event time (us) of each pass of a multi-pass plan: the first k
+    passes timed alone (tcfft_exec_passes), differences of the prefixes."""
+    pref = [0.0]
+    for k in range(1, plan.num_launches + 1):
+        pref.append(time_launches(lambda: plan.run_passes(x, k, out=y, stream=stream), reps,
+                                  stream) * 1e6)
+    return [round(pref[k] - pref[k - 1], 2) for k in range(1, len(pref))]
+
+
 def accuracy_sample(plan, x_dev, y_dev, x_host, tones, rng, nsample=32):
     """Relative L2 of sampled transforms (random rows + every tone row) vs the oracle."""
     import oracle
@@ -443,19 +464,26 @@ def main():
                   "rel_l2_max": emax, "rel_l2_rms": erms, "eq5": eq5, "rows_checked": ns}
         log(f"N={n}: {per[n]}")
 
-    # dominant kernel: the single-launch size with the largest time
-    single = [n for n in SIZES if plans[n].num_launches == 1] or list(SIZES)
-    dom = max(single, key=lambda n: per[n]["us"])
+    # dominant plan: the size whose plan takes the largest share of the step
+    # (a multi-pass plan counts as one unit: its algorithmic bytes are one
+    # round trip, 8 B per point, whatever its pass count)
+    dom = max(SIZES, key=lambda n: per[n]["us"])
+    for n in SIZES:
+        per[n]["choice"] = plans[n].describe()["choice"]
+        per[n]["kernels"] = [kernel_name(q) for q in plans[n].describe()["passes"]]
+        per[n]["hbm_frac_alg"] = round(8.0 * TOTAL_POINTS / (per[n]["us"] * 1e-6) / 1e9 /
+                                       HBM_PEAK_GBS, 4)
+        if plans[n].num_launches > 1:
+            per[n]["pass_us"] = pass_times(plans[n], xd[n], yd[n], stream)
     dom_bytes = 8.0 * TOTAL_POINTS
-    dk = plans[dom].describe()["passes"][0]
-    kname = (f"row_kernel<{dk['L']}, {dk['radices'][0] if dk['radices'][0] != 16 else 1}, "
-             f"{dk['NT']}, false, false, 0>")
-    per[dom]["choice"] = plans[dom].describe()["choice"]
+    knames = per[dom]["kernels"]
     achieved = dom_bytes / (per[dom]["us"] * 1e-6) / 1e9
+    traffic = [measured_traffic(k) for k in knames]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-                "kernel": f"{kname} N={dom} batch={TOTAL_POINTS // dom}",
-                "alg_bytes_per_launch": int(dom_bytes)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": sum(traffic) if all(t is not None for t in traffic) else None,
+                "kernel": " + ".join(knames) + f" N={dom} batch={TOTAL_POINTS // dom}",
+                "alg_bytes_per_launch": int(dom_bytes), "launches": len(knames)}
 
     comparator = None
     if not args.no_comparator:
@@ -497,6 +525,9 @@ def main():
                                "(512 MiB FP16 each), uniform[-1,1] + 1% unit tones, forward",
                    "points_per_size": TOTAL_POINTS, "precision": "fp16 storage, fp32 accumulate"},
         "hbm_frac_alg": round(hbm_frac, 4),
+        "roofline_step": {"achieved": round(8.0 * TOTAL_POINTS * len(SIZES) / (ms_per_step * 1e-3) / 1e9, 1),
+                          "frac": round(hbm_frac, 4), "unit": "GB/s",
+                          "alg_bytes_per_step": int(8 * TOTAL_POINTS * len(SIZES))},
         "per_size": {str(k): v for k, v in per.items()},
         "roofline": roofline,
         "comparator_fp32_radix2": comparator,

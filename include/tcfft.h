@@ -159,6 +159,44 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
 tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
                                void* stream);
 
+/*
+ * One device's share of a distributed 1D transform (the single-GPU kernels of
+ * a multi-device four-step FFT; the paper's Sec. 6 names distributed FFT
+ * frameworks as the place its kernels plug into).  The length N is split as
+ * N = N1 * M (Sec. 2.1, Eq. 3 with n = n1 M + m and k = k1 + N1 k'), N1 the
+ * first factor of the library's own long-1D plan (tcfft_plan_describe,
+ * "shard_n1"), and the M columns m are dealt out to G = nshards devices in
+ * slabs of M/G; device g = shard holds m = g M/G + m_l, m_l < M/G.  With
+ * n1l = N1/G and ml = M/G, per transform b of the batch (all offsets in
+ * complex points, b * N/G apart):
+ *   step 1  in:  x[n1 M + g ml + m_l] at n1 ml + m_l            ([N1][ml])
+ *           out: Z[k1][m] = 2^-s1 W_N^{m k1} sum_{n1} x[n1 M + m] W_N1^{n1 k1}
+ *                at h (ml n1l) + m_l n1l + k1_l, k1 = h n1l + k1_l
+ *                ([G][ml][n1l]: block h is the contiguous chunk for device h)
+ *   exchange (the caller's all-to-all): device h receives block h of every
+ *           device g and concatenates them in g order, giving [M][n1l]
+ *           (row m = g ml + m_l)
+ *   step 2  in:  that [M][n1l] array on device h
+ *           out: X[k' N1 + h n1l + k1_l] * 2^-S at k' n1l + k1_l ([M][n1l])
+ * s1 is passes[0].scale of the description and S = tcfft_plan_scale_log2().
+ * Layouts as tcfft_exec (FP16 or split; split buffers hold the hi plane of
+ * batch * N/G points, then the lo plane); every buffer of both steps holds
+ * batch * N/G points (tcfft_plan_buffer_bytes).  Requires N > 16384,
+ * nshards a power of two >= 2 with N1/nshards >= 4 and M/nshards >= 8,
+ * 0 <= shard < nshards; TCFFT_FLAG_NO_SCALE allowed, TUNE ignored, REAL
+ * rejected.  tcfft_exec, tcfft_exec_passes and tcfft_exec_many refuse shard
+ * plans (UNSUPPORTED / INVALID_ARG): the two steps surround an exchange.
+ * tcfft_exec_shard runs step 1 or 2; `in` and `out` must differ.
+ * Errors: INVALID_ARG (bad shard, step, pointers), UNSUPPORTED (sizes),
+ * NO_DEVICE, ALLOC, LAUNCH.  tcfft_shard_dry_run is the device-free planner
+ * (returns the JSON length, or -(status)).
+ */
+tcfft_status tcfft_plan_create_shard(tcfft_plan* out, int64_t n, int64_t batch, int dir,
+                                     int precision, int nshards, int shard, unsigned flags);
+tcfft_status tcfft_exec_shard(tcfft_plan plan, int step, const void* in, void* out, void* stream);
+int tcfft_shard_dry_run(int64_t n, int64_t batch, int dir, int precision, int nshards, int shard,
+                        unsigned flags, char* buf, size_t len);
+
 /* Releases the plan and its device memory (synchronises the device first).
  * NULL is accepted.  Errors: none besides INTERNAL. */
 tcfft_status tcfft_plan_destroy(tcfft_plan plan);

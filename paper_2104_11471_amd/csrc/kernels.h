@@ -31,12 +31,21 @@ struct KParams {
   // log2 of blocks, q and xdiv (all powers of two)
   int32_t blocks_log2, q_log2, xdiv_log2;
   float r0scale2;          // plane kernel: scale of the column half's radix-R0 stage
+  // column kernel, extra twiddle: global index of the pass's column 0 (a shard
+  // of a distributed four-step transform holds columns xoff, xoff + 1, ...)
+  int64_t xoff;
+  // transposed store in blocks: output k of local column ci lands at
+  // (k >> tblk_log2) * tblk_stride + (ci << tblk_log2) + (k & (2^tblk_log2 - 1));
+  // tblk_log2 = log2(L) is the plain transposed store (row ci of L outputs)
+  int64_t tblk_stride;
+  int32_t tblk_log2;
+  int32_t pad0;
 };
 
 // The same struct is read by host code (x86-64) and, in grouped launches, by
 // device code from a table in device memory: both ABIs lay it out alike
 // (8-byte pointers and int64_t, 4-byte float/int32, natural alignment).
-static_assert(sizeof(KParams) == 168, "KParams layout changed: host and device must agree");
+static_assert(sizeof(KParams) == 192, "KParams layout changed: host and device must agree");
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
@@ -110,5 +119,6 @@ void launch_r2c_post(const void* z, void* x, const float2* tw, int64_t M, int64_
                      bool split, hipStream_t s);
 void launch_c2r_pre(const void* x, void* z, const float2* tw, int64_t M, int64_t batch,
                     bool split, hipStream_t s);
+
 
 }  // namespace tcfft

@@ -1028,7 +1028,7 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
         for (int t = 0; t < 4; ++t) w[t][j] = v;
       } else if constexpr (XTW) {
         const uint32_t k = (uint32_t)(restl + (L / 16) * (4 * g + j));  // natural output index
-        const uint32_t ci = (uint32_t)(cx.i0 + c);
+        const uint32_t ci = (uint32_t)(kp.xoff + cx.i0 + c);
         if (kp.xdiv == 1) {
           // W_M^{(ci + t) k} = W_M^{ci k} * (W_M^k)^t
           const float2 a = xtwiddle(kp, ci, k);
@@ -1111,7 +1111,9 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
         h[i] = lds_ld1(lds, j * C + c);
         if constexpr (SPLIT) l[i] = lds_ld1(ldsl, j * C + c);
       }
-      const int64_t a = cx.out_base + (int64_t)c * L + k0;
+      const int tb = kp.tblk_log2;
+      const int64_t a = cx.out_base + (int64_t)(k0 >> tb) * kp.tblk_stride +
+                        ((int64_t)c << tb) + (k0 & ((1 << tb) - 1));
       gst4(kp.out + a, h);
       if constexpr (SPLIT) gst4(kp.out + kp.out_plane + a, l);
     }
@@ -1243,7 +1245,7 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
   cx.i0 = (wg & (kp.blocks - 1)) * C;
   cx.in_base = cx.outer * kp.in_outer + cx.i0;
   if constexpr (TSTORE)
-    cx.out_base = cx.outer * kp.out_outer + cx.i0 * L;
+    cx.out_base = cx.outer * kp.out_outer + (cx.i0 << kp.tblk_log2);
   else
     cx.out_base = cx.outer * kp.out_outer + (cx.i0 >> kp.q_log2) * kp.qstride + (cx.i0 & (kp.q - 1));
   const FOps f = load_fops<SPLIT>(kp.fimg);

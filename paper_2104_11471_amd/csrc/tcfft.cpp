@@ -63,6 +63,10 @@ struct PassSpec {
   // buffers: 0 = user in, 1 = user out, 2 = workspace
   int src = 0, dst = 1;
   int scale = 0;  // this pass's scale exponent
+  // shard of a distributed transform: global index of column 0 for the extra
+  // twiddle, and the blocked transposed store (0 = plain rows of L outputs)
+  int64_t xoff = 0;
+  int64_t tblk = 0, tblk_stride = 0;
 };
 
 struct Desc {
@@ -72,6 +76,8 @@ struct Desc {
   int dir = -1;
   int prec = 0;
   unsigned flags = 0;
+  int nshards = 0;  // > 0: one shard of a distributed four-step 1D transform
+  int shard = 0;
 };
 
 // Tunable planner knobs (the autotuner sweeps these).
@@ -103,6 +109,9 @@ struct PlanSpec {
   int64_t real_n = 0;
   bool real_fused = false;  // the real step runs inside the (single) row pass
   size_t zbuf_bytes = 0;  // unfused: the complex transform's side of the elementwise pass
+  // shard plans: passes[0] is step 1 (before the exchange), the rest step 2;
+  // n1 = the step-1 length N1
+  int64_t shard_n1 = 0;
 };
 
 tcfft_status col_choice(int L, int64_t inner, int cmax, bool split, bool xtw, bool tstore,
@@ -272,6 +281,13 @@ tcfft_status validate(const Desc& d) {
   if (d.flags & TCFFT_FLAG_REAL) {
     if (d.rank != 1 || d.prec == TCFFT_PREC_FP32_RADIX2 || d.nx < 32) return TCFFT_ERR_UNSUPPORTED;
   }
+  if (d.nshards != 0) {
+    if (d.nshards < 2 || !is_pow2(d.nshards) || d.shard < 0 || d.shard >= d.nshards)
+      return TCFFT_ERR_INVALID_ARG;
+    if (d.rank != 1 || (d.flags & TCFFT_FLAG_REAL) || d.prec == TCFFT_PREC_FP32_RADIX2 ||
+        d.nx <= kMaxRowL)
+      return TCFFT_ERR_UNSUPPORTED;
+  }
   if (d.nx * d.ny > kMaxPointsPerPlan / d.nz) return TCFFT_ERR_UNSUPPORTED;
   const int64_t npts = d.nx * d.ny * d.nz;
   if (d.batch > kMaxPointsPerPlan / npts) return TCFFT_ERR_UNSUPPORTED;
@@ -335,7 +351,44 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     *out = ps;
     return TCFFT_OK;
   }
-  if (d.rank == 1) {
+  if (d.nshards > 0) {
+    // one shard of the four-step split N = N1 * M over G = nshards devices
+    // (Sec. 2.1, Eq. 3, with the columns m dealt out in slabs of M / G):
+    // step 1 runs the N1-point DFTs of the shard's columns m = g M/G + m_l
+    // with the twiddle W_N^{m k1} at their global m, storing Z[h][m_l][k1_l]
+    // (k1 = h N1/G + k1_l) so that block h is the contiguous chunk for device
+    // h; after the exchange, device h holds [m][k1_l] and step 2 runs the
+    // M-point DFTs over m (one column pass, or two when M > 2048), writing
+    // X[k' N1 + h N1/G + k1_l] at [k'][k1_l].
+    const int64_t N = d.nx, G = d.nshards;
+    const std::vector<int> f = long_split(N);
+    const int64_t N1 = f[0], M = N / N1, n1l = N1 / G, ml = M / G;
+    if (n1l < 4 || ml < 8) return TCFFT_ERR_UNSUPPORTED;
+    ps.shard_n1 = N1;
+    ps.buf_bytes = (size_t)(N / G * B) * elt;
+    ps.in_bytes = ps.out_bytes = ps.buf_bytes;
+    st = add_col_pass(ps, (int)N1, ml, B, N / G, N / G, 0, 1, 0, true, N, 1, 0, 1);
+    if (!st) {
+      PassSpec& p1 = ps.passes.back();
+      p1.xoff = d.shard * ml;
+      p1.tblk = n1l;
+      p1.tblk_stride = ml * n1l;
+    }
+    if (!st && f.size() == 2) {
+      st = add_col_pass(ps, (int)M, n1l, B, M * n1l, M * n1l, n1l, n1l, 0, false, 0, 1, 0, 1);
+    } else if (!st && f.size() == 3) {
+      const int64_t M2 = f[1], M3 = f[2];
+      // over m2 (stride M3 n1l), twiddle W_M^{m3 k2}, store [m3][k2][k1_l]
+      st = add_col_pass(ps, (int)M2, M3 * n1l, B, M * n1l, M * n1l, n1l, n1l, M2 * n1l, false, M,
+                        n1l, 0, 1, n1l);
+      // over m3 (stride M2 n1l), in place -> [k3 M2 + k2][k1_l]
+      if (!st)
+        st = add_col_pass(ps, (int)M3, M2 * n1l, B, M * n1l, M * n1l, M2 * n1l, M2 * n1l, 0, false,
+                          0, 1, 1, 1);
+    } else if (!st) {
+      st = TCFFT_ERR_UNSUPPORTED;
+    }
+  } else if (d.rank == 1) {
     const int64_t N = d.nx;
     if (N <= kMaxRowL) {
       st = add_row_pass(ps, (int)N, B, 0, 1);
@@ -431,7 +484,7 @@ std::string describe(const PlanSpec& ps) {
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"input_bytes\":%zu,\"output_bytes\":%zu,"
                 "\"workspace_bytes\":%zu,\"real\":%lld,\"real_kernel\":\"%s\","
                 "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
-                "\"tuned_us\":%.2f,\"passes\":[",
+                "\"tuned_us\":%.2f,\"nshards\":%d,\"shard\":%d,\"shard_n1\":%lld,\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank >= 2 ? "," : "",
                 ps.d.rank >= 2 ? std::to_string(ps.d.ny).c_str() : "", ps.d.rank == 3 ? "," : "",
                 ps.d.rank == 3 ? std::to_string(ps.d.nz).c_str() : "", (long long)ps.d.batch, ps.d.dir,
@@ -441,7 +494,7 @@ std::string describe(const PlanSpec& ps) {
                 ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
                 ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
-                ps.tuned_us);
+                ps.tuned_us, ps.d.nshards, ps.d.shard, (long long)ps.shard_n1);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
@@ -716,6 +769,9 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.blocks_log2 = sp.blocks > 0 ? ilog2(sp.blocks) : 0;
   kp.q_log2 = ilog2(sp.q);
   kp.xdiv_log2 = ilog2(sp.xdiv);
+  kp.xoff = sp.xoff;
+  kp.tblk_log2 = ilog2(sp.tblk > 0 ? sp.tblk : sp.key.L);
+  kp.tblk_stride = sp.tblk_stride;
   if (sp.key.real) {  // spectrum lines hold M + 1 words; the row pass reads W_N from xtw_lo
     if (split && sp.key.real == 1) kp.out_plane = (ps.npts + 1) * batch;
     if (split && sp.key.real == 2) kp.in_plane = (ps.npts + 1) * batch;
@@ -812,6 +868,24 @@ tcfft_status exec_real(tcfft_plan_s* p, const void* in, void* out, hipStream_t s
 
 tcfft_status exec_any(tcfft_plan_s* p, const void* in, void* out, hipStream_t s) {
   return p->spec.real_n > 0 ? exec_real(p, in, out, s) : exec_impl(p, in, out, s);
+}
+
+// One step of a shard plan: step 1 is pass 0, step 2 the remaining passes
+// (the first reads `in`, every later one runs in place in `out`).
+tcfft_status exec_shard_step(tcfft_plan_s* p, int step, const void* in, void* out, hipStream_t s) {
+  const size_t first = step == 1 ? 0 : 1, last = step == 1 ? 1 : p->dp.size();
+  for (size_t i = first; i < last; ++i) {
+    const DevPass& dpp = p->dp[i];
+    int64_t grid = 0;
+    KParams kp = make_kparams(p, dpp, in, out, p->spec.d.batch, p->ws, &grid);
+    void* args[] = {&kp};
+    if (hipLaunchKernel((const void*)dpp.fn.single, dim3((unsigned)grid), dim3(dpp.spec.key.NT),
+                        args, dpp.spec.lds, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_LAUNCH;
+    }
+  }
+  return TCFFT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1302,8 +1376,9 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
   Choice ch;
   bool tuned = false;
   double tuned_us = 0.0;
-  // a real plan shares the tuned choice of its complex transform
-  if ((st = choose(complex_desc(d), &ch, &tuned, &tuned_us))) return st;
+  // a real plan shares the tuned choice of its complex transform; shard plans
+  // keep the default factorisation (every device must split N alike)
+  if (d.nshards == 0 && (st = choose(complex_desc(d), &ch, &tuned, &tuned_us))) return st;
   if ((st = build_spec(d, ch, &ps))) return st;
   ps.tuned = tuned;
   ps.tuned_us = tuned_us;
@@ -1364,25 +1439,78 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream) {
   if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out) || real_overlap(plan, in, out)) return TCFFT_ERR_INVALID_ARG;
+  if (plan->spec.d.nshards > 0) return TCFFT_ERR_UNSUPPORTED;  // two steps around an exchange
   return exec_any(plan, in, out, (hipStream_t)stream);
+}
+
+tcfft_status tcfft_plan_create_shard(tcfft_plan* out, int64_t n, int64_t batch, int dir,
+                                     int precision, int nshards, int shard, unsigned flags) {
+  if (!out) return TCFFT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (nshards == 0) return TCFFT_ERR_INVALID_ARG;
+  Desc d;
+  d.nx = n;
+  d.batch = batch;
+  d.dir = dir;
+  d.prec = precision;
+  d.flags = flags & ~(unsigned)TCFFT_FLAG_TUNE;
+  d.nshards = nshards;
+  d.shard = shard;
+  try {
+    return create_impl(d, out);
+  } catch (...) {
+    return TCFFT_ERR_INTERNAL;
+  }
+}
+
+int tcfft_shard_dry_run(int64_t n, int64_t batch, int dir, int precision, int nshards, int shard,
+                        unsigned flags, char* buf, size_t len) {
+  if (nshards == 0) return -(int)TCFFT_ERR_INVALID_ARG;
+  Desc d;
+  d.nx = n;
+  d.batch = batch;
+  d.dir = dir;
+  d.prec = precision;
+  d.flags = flags & ~(unsigned)TCFFT_FLAG_TUNE;
+  d.nshards = nshards;
+  d.shard = shard;
+  PlanSpec ps;
+  tcfft_status st = build_spec(d, Choice{}, &ps);
+  if (st) return -(int)st;
+  return copy_out(describe(ps), buf, len);
+}
+
+tcfft_status tcfft_exec_shard(tcfft_plan plan, int step, const void* in, void* out, void* stream) {
+  if (!plan || !in || !out || plan->spec.d.nshards == 0 || (step != 1 && step != 2))
+    return TCFFT_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out) || in == out) return TCFFT_ERR_INVALID_ARG;
+  try {
+    return exec_shard_step(plan, step, in, out, (hipStream_t)stream);
+  } catch (...) {
+    return TCFFT_ERR_INTERNAL;
+  }
 }
 
 tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
                                void* stream) {
   if (!plan || !in || !out || in == out) return TCFFT_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
-  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0)
+  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0 ||
+      plan->spec.d.nshards > 0)
     return TCFFT_ERR_UNSUPPORTED;
   if (npasses < 1 || npasses > (int)plan->dp.size()) return TCFFT_ERR_INVALID_ARG;
   return exec_impl(plan, in, out, (hipStream_t)stream, npasses);
 }
 
-tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
-                             int njobs, void* stream) {
+}  // extern "C"
+
+namespace {
+tcfft_status check_many(const tcfft_plan* plans, const void* const* in, void* const* out,
+                        int njobs) {
   if (njobs < 0 || (njobs > 0 && (!plans || !in || !out))) return TCFFT_ERR_INVALID_ARG;
   for (int j = 0; j < njobs; ++j)
     if (!plans[j] || !in[j] || !out[j] || !aligned16(in[j]) || !aligned16(out[j]) ||
-        real_overlap(plans[j], in[j], out[j]))
+        real_overlap(plans[j], in[j], out[j]) || plans[j]->spec.d.nshards > 0)
       return TCFFT_ERR_INVALID_ARG;
   // a plan with a workspace (multi-pass) or a spectrum buffer (real plans
   // with a separate spectrum pass) can serve only one job of a grouped launch:
@@ -1392,7 +1520,16 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
     for (int i = 0; i < j; ++i)
       if (plans[i] == plans[j]) return TCFFT_ERR_INVALID_ARG;
   }
-  if (njobs == 0) return TCFFT_OK;
+  return TCFFT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
+                             int njobs, void* stream) {
+  tcfft_status st = check_many(plans, in, out, njobs);
+  if (st || njobs == 0) return st;
   try {
     return exec_many_impl(plans, in, out, njobs, (hipStream_t)stream);
   } catch (...) {

@@ -38,7 +38,8 @@ EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", 
            "tcfft_tune_cache_size", "tcfft_tune_cache_save", "tcfft_tune_cache_load",
            "tcfft_tune_cache_clear", "tcfft_server_create", "tcfft_server_prepare",
            "tcfft_server_submit", "tcfft_server_poll", "tcfft_server_wait_idle",
-           "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns"]
+           "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns",
+           "tcfft_plan_create_shard", "tcfft_exec_shard", "tcfft_shard_dry_run"]
 
 
 class TcfftError(RuntimeError):
@@ -98,6 +99,15 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_tune_cache_load.restype = ctypes.c_int
     lib.tcfft_tune_cache_clear.argtypes = []
     lib.tcfft_tune_cache_clear.restype = None
+    lib.tcfft_plan_create_shard.argtypes = [P(vp), i64, i64, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_uint]
+    lib.tcfft_plan_create_shard.restype = ctypes.c_int
+    lib.tcfft_exec_shard.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.tcfft_exec_shard.restype = ctypes.c_int
+    lib.tcfft_shard_dry_run.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_uint, ctypes.c_char_p,
+                                        ctypes.c_size_t]
+    lib.tcfft_shard_dry_run.restype = ctypes.c_int
     for name in ("tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec",
                  "tcfft_exec_many", "tcfft_exec_passes", "tcfft_plan_destroy",
                  "tcfft_plan_scale_log2", "tcfft_plan_num_launches", "tcfft_plan_describe",
@@ -324,3 +334,63 @@ def exec_many(plans, xs, outs, stream=None) -> None:
     st = lib.tcfft_exec_many(hp, ip, op, n, VP(s.cuda_stream))
     if st != 0:
         raise TcfftError(st, "tcfft_exec_many")
+
+
+def shard_dry_run(n: int, batch: int, nshards: int, shard: int, direction: int = FORWARD,
+                  precision="fp16", flags: int = 0) -> dict:
+    """Planner only (no device): the JSON plan of one shard."""
+    buf = ctypes.create_string_buffer(8192)
+    r = lib.tcfft_shard_dry_run(int(n), int(batch), int(direction), _prec(precision),
+                                int(nshards), int(shard), int(flags), buf, len(buf))
+    if r < 0:
+        raise TcfftError(-r, "tcfft_shard_dry_run")
+    return json.loads(buf.value.decode())
+
+
+class ShardPlan(Plan):
+    """One device's share of a distributed N-point transform over `nshards`
+    devices (tcfft_plan_create_shard): ``step1`` before the caller's
+    all-to-all, ``step2`` after it.  Tensors hold ``batch * N / nshards``
+    points: ``(batch, N // nshards, 2)`` float16 (split: ``(2, ...)``)."""
+
+    def __init__(self, n: int, batch: int, nshards: int, shard: int, direction: int = FORWARD,
+                 precision="fp16", flags: int = 0):
+        self.dims = (int(n),)
+        self.batch = int(batch)
+        self.direction = int(direction)
+        self.precision = _prec(precision)
+        self.flags = int(flags)
+        self.nshards = int(nshards)
+        self.shard = int(shard)
+        h = ctypes.c_void_p()
+        st = lib.tcfft_plan_create_shard(ctypes.byref(h), int(n), self.batch, self.direction,
+                                         self.precision, self.nshards, self.shard, self.flags)
+        if st != 0:
+            raise TcfftError(st, "tcfft_plan_create_shard")
+        self._h = h
+
+    def _side(self, real_side: bool) -> tuple:
+        core = (self.batch, self.dims[0] // self.nshards, 2)
+        return (2, *core) if self.precision == PREC_SPLIT_FP16 else core
+
+    def _step(self, step: int, x, out, stream):
+        import torch
+        self._check(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(out, "output")
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        st = lib.tcfft_exec_shard(self._h, int(step), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+        if st != 0:
+            raise TcfftError(st, "tcfft_exec_shard")
+        return out
+
+    def step1(self, x, out=None, stream=None):
+        return self._step(1, x, out, stream)
+
+    def step2(self, x, out=None, stream=None):
+        return self._step(2, x, out, stream)
+
+    def __call__(self, x, out=None, stream=None):
+        raise TcfftError(2, "a shard plan runs step1 and step2 around an exchange")
