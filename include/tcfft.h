@@ -29,8 +29,14 @@
  * Output is in natural order, in the same layout as the input.  in == out is
  * allowed (in-place).
  *
- * Errors: every entry point returns a status code; nothing aborts or prints.
+ * Errors: every entry point returns a status code; nothing aborts.  Nothing
+ * prints unless the environment variable TCFFT_LOG is set (non-empty, not
+ * "0"): then plan creation writes each plan's JSON description (as
+ * tcfft_plan_describe) and every failing entry point its status to stderr.
  * Kernel faults surface asynchronously at the caller's next synchronisation.
+ * Testing hook: while TCFFT_TEST_FAIL_ALLOC is set, every device allocation
+ * of plan and server creation fails (ALLOC), so callers can exercise their
+ * allocation-failure paths.
  */
 #ifndef TCFFT_H_
 #define TCFFT_H_
@@ -51,7 +57,9 @@ typedef enum {
   TCFFT_ERR_NO_DEVICE = 3,   /* no gfx950 device visible */
   TCFFT_ERR_ALLOC = 4,       /* device allocation failed */
   TCFFT_ERR_LAUNCH = 5,      /* a kernel launch was rejected by the runtime */
-  TCFFT_ERR_INTERNAL = 6
+  TCFFT_ERR_INTERNAL = 6,
+  TCFFT_ERR_TIMEOUT = 7,     /* serving: the request waited in the queue past queue_timeout_us */
+  TCFFT_ERR_CANCELLED = 8    /* serving: the request was cancelled before it was admitted */
 } tcfft_status;
 
 #define TCFFT_FORWARD (-1)
@@ -285,6 +293,8 @@ typedef struct {
                               (descriptor tables are rewritten in device memory per batch) */
   int batch_window_us;     /* while other slots are busy, hold a batch until its oldest
                               request has waited this long (0 = dispatch at once) */
+  int queue_timeout_us;    /* > 0: a request still queued (not admitted) this long after its
+                              submission completes with TCFFT_ERR_TIMEOUT instead of running */
 } tcfft_server_config;
 
 typedef struct {
@@ -323,6 +333,11 @@ tcfft_status tcfft_server_submit(tcfft_server s, const tcfft_request* req);
 /* Moves up to `max` completion records into `out`; returns how many, or
  * -(status) on bad arguments. */
 int tcfft_server_poll(tcfft_server s, tcfft_completion* out, int max);
+/* Cancels every queued (not yet admitted) request with this tag: each
+ * completes with TCFFT_ERR_CANCELLED.  Requests already launched run to
+ * completion.  Returns how many were cancelled, or -(status) for a NULL
+ * server. */
+int tcfft_server_cancel(tcfft_server s, uint64_t tag);
 /* Waits until nothing is queued or in flight (timeout_ms < 0: forever);
  * INTERNAL on timeout. */
 tcfft_status tcfft_server_wait_idle(tcfft_server s, int64_t timeout_ms);

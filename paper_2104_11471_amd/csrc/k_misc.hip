@@ -52,16 +52,19 @@ void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mul
                      tw, count, modulus, mult, sgn);
 }
 
-__global__ void gen_fimg_kernel(h8* img, double sgn, double scale) {
+// Lane = 16 g + m holds row m of the A operand, K entries of input rows
+// r = 4g..4g+3; entry (m, r) = F_16[m][r] W_{16 R}^{k r} = W_{16 R}^{r (R m + k)}
+// (R = 1, k = 0: the plain radix-16 matrix).
+__global__ void gen_fimg_kernel(h8* img, double sgn, double scale, int R, int k) {
   const int lane = threadIdx.x;  // 64 lanes
   const int g = lane >> 4, m = lane & 15;
   h8 rh, ih, rl, il;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = 4 * g + i;
-    const int e = (m * r) & 15;
+    const int e = (r * (R * m + k)) % (16 * R);
     double sn, cs;
-    sincospi(2.0 * (double)e / 16.0, &sn, &cs);
+    sincospi(2.0 * (double)e / (16.0 * R), &sn, &cs);
     const double fr = cs * scale, fi = sgn * sn * scale;
     // Yr row: [Fr, -Fi]; Yi row: [Fi, Fr]  (pairs = re/im halves of input row r)
     const double vr[2] = {fr, -fi}, vi[2] = {fi, fr};
@@ -83,7 +86,17 @@ __global__ void gen_fimg_kernel(h8* img, double sgn, double scale) {
 
 void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s) {
   hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<h8*>(img), sgn,
-                     scale);
+                     scale, 1, 0);
+}
+
+void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s) {
+  for (int slot = 0; slot < R; ++slot) {
+    // inverse plans: slot k' holds A_k with k = (R - k') mod R (the kernels
+    // follow the forward sign, whose W^{k' d} is the inverse W^{k d})
+    const int k = sgn > 0 ? (R - slot) % R : slot;
+    hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<h8*>(img) + 256 * slot, sgn, scale, R, k);
+  }
 }
 
 // Autotuner scratch data: FP16 complex words with re, im in [-1, 1) from a

@@ -40,12 +40,15 @@ struct KParams {
   int64_t tblk_stride;
   int32_t tblk_log2;
   int32_t pad0;
+  // A operands of the matrix-core radix-R0 x radix-16 block (R0 images A_k,
+  // 256 h8 each: Yr-hi, Yi-hi, Yr-lo, Yi-lo), pass-specific
+  const void* fimg2;
 };
 
 // The same struct is read by host code (x86-64) and, in grouped launches, by
 // device code from a table in device memory: both ABIs lay it out alike
 // (8-byte pointers and int64_t, 4-byte float/int32, natural alignment).
-static_assert(sizeof(KParams) == 192, "KParams layout changed: host and device must agree");
+static_assert(sizeof(KParams) == 200, "KParams layout changed: host and device must agree");
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
@@ -109,6 +112,10 @@ void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mul
 // Radix-16 A-operand images, F scaled by `scale` (a power of two):
 // [0] Yr-hi, [1] Yi-hi, [2] Yr-lo, [3] Yi-lo; 64 lanes x 8 halves each.
 void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s);
+// A_k = F_16 . diag(W_{16 R}^{k m}) scaled by `scale`, for k = 0..R-1, at
+// img + 256 k (h8 units; inverse sgn: slot k' holds k = (R - k') mod R), the
+// same four images as launch_gen_fimg.
+void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s);
 void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s);
 
 // Real-input transforms around an M-point complex transform (N = 2M reals).
@@ -119,6 +126,5 @@ void launch_r2c_post(const void* z, void* x, const float2* tw, int64_t M, int64_
                      bool split, hipStream_t s);
 void launch_c2r_pre(const void* x, void* z, const float2* tw, int64_t M, int64_t batch,
                     bool split, hipStream_t s);
-
 
 }  // namespace tcfft

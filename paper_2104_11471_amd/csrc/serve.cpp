@@ -20,6 +20,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -160,6 +161,46 @@ bool reap(tcfft_server_s* s) {
   return any;
 }
 
+// Completes queued requests with `status` (no slot: start = done = now).
+void complete_unadmitted(tcfft_server_s* s, const std::vector<Req>& reqs, int status) {
+  if (reqs.empty()) return;
+  const int64_t t = now_ns();
+  std::lock_guard<std::mutex> lk(s->done_mu);
+  for (const Req& q : reqs) {
+    tcfft_completion c{};
+    c.tag = q.r.tag;
+    c.status = status;
+    c.t_submit_ns = q.t_submit;
+    c.t_start_ns = t;
+    c.t_done_ns = t;
+    c.batch_id = -1;
+    c.batch_jobs = 0;
+    s->done.push_back(c);
+  }
+}
+
+// Drops queued requests that waited past queue_timeout_us (they complete with
+// TCFFT_ERR_TIMEOUT); returns true when any expired.
+bool expire(tcfft_server_s* s) {
+  if (s->cfg.queue_timeout_us <= 0) return false;
+  std::vector<Req> gone;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t limit = now_ns() - (int64_t)s->cfg.queue_timeout_us * 1000;
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+      if (it->t_submit < limit) {
+        gone.push_back(*it);
+        it = s->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    s->stats.completed += (int64_t)gone.size();
+  }
+  complete_unadmitted(s, gone, TCFFT_ERR_TIMEOUT);
+  return !gone.empty();
+}
+
 // Admits a FIFO prefix of the queue into idle slot `sl` and launches it.
 // While other slots keep the GPU busy, a batch is held back until its oldest
 // request has waited batch_window_us (so batches grow with the load); an idle
@@ -224,6 +265,7 @@ void run(tcfft_server_s* s) {
   (void)hipSetDevice(s->device);
   while (!s->stop.load()) {
     bool progressed = reap(s);
+    progressed = expire(s) || progressed;
     for (Slot& sl : s->slots)
       if (!sl.busy && dispatch(s, sl)) progressed = true;
     if (progressed) continue;
@@ -264,7 +306,7 @@ tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* c
   if (!out || !cfg) return TCFFT_ERR_INVALID_ARG;
   *out = nullptr;
   if (cfg->nslots < 1 || cfg->nslots > 16 || cfg->max_batch_jobs < 1 ||
-      cfg->mem_budget_bytes == 0 || cfg->batch_window_us < 0)
+      cfg->mem_budget_bytes == 0 || cfg->batch_window_us < 0 || cfg->queue_timeout_us < 0)
     return TCFFT_ERR_INVALID_ARG;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
@@ -282,6 +324,7 @@ tcfft_status tcfft_server_create(tcfft_server* out, const tcfft_server_config* c
     sl.graphs = new tcfft::GraphCache();
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+        std::getenv("TCFFT_TEST_FAIL_ALLOC") != nullptr ||
         hipMalloc(&sl.arena, arena) != hipSuccess || hipMalloc(&sl.desc, desc) != hipSuccess) {
       (void)hipGetLastError();
       for (Slot& t : s->slots) {
@@ -332,6 +375,25 @@ tcfft_status tcfft_server_submit(tcfft_server s, const tcfft_request* req) {
   s->stats.submitted += 1;
   s->cv.notify_one();
   return TCFFT_OK;
+}
+
+int tcfft_server_cancel(tcfft_server s, uint64_t tag) {
+  if (!s) return -(int)TCFFT_ERR_INVALID_ARG;
+  std::vector<Req> gone;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+      if (it->r.tag == tag) {
+        gone.push_back(*it);
+        it = s->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    s->stats.completed += (int64_t)gone.size();
+  }
+  complete_unadmitted(s, gone, TCFFT_ERR_CANCELLED);
+  return (int)gone.size();
 }
 
 int tcfft_server_poll(tcfft_server s, tcfft_completion* out, int max) {

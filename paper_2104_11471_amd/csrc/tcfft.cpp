@@ -32,6 +32,17 @@ constexpr int kMaxColL = 2048;   // largest strided length handled in one pass
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// TCFFT_LOG set (non-empty, not "0"): plan descriptions and failing statuses
+// go to stderr.
+bool log_on() {
+  const char* v = std::getenv("TCFFT_LOG");
+  return v && *v && std::strcmp(v, "0") != 0;
+}
+tcfft_status logged(tcfft_status st, const char* what) {
+  if (st != TCFFT_OK && log_on()) std::fprintf(stderr, "tcfft: %s: status %d\n", what, (int)st);
+  return st;
+}
 int ilog2(int64_t n) {
   int l = 0;
   while (((int64_t)1 << l) < n) ++l;
@@ -365,6 +376,9 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     const int64_t N1 = f[0], M = N / N1, n1l = N1 / G, ml = M / G;
     if (n1l < 4 || ml < 8) return TCFFT_ERR_UNSUPPORTED;
     ps.shard_n1 = N1;
+    // a shard buffer holds N/G points per transform: the kernels place the
+    // lo plane of split data npts * batch words after the hi plane
+    ps.npts = N / G;
     ps.buf_bytes = (size_t)(N / G * B) * elt;
     ps.in_bytes = ps.out_bytes = ps.buf_bytes;
     st = add_col_pass(ps, (int)N1, ml, B, N / G, N / G, 0, 1, 0, true, N, 1, 0, 1);
@@ -484,7 +498,8 @@ std::string describe(const PlanSpec& ps) {
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"input_bytes\":%zu,\"output_bytes\":%zu,"
                 "\"workspace_bytes\":%zu,\"real\":%lld,\"real_kernel\":\"%s\","
                 "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
-                "\"tuned_us\":%.2f,\"nshards\":%d,\"shard\":%d,\"shard_n1\":%lld,\"passes\":[",
+                "\"tuned_us\":%.2f,\"nshards\":%d,\"shard\":%d,\"shard_n1\":%lld,\"points\":%lld,"
+                "\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank >= 2 ? "," : "",
                 ps.d.rank >= 2 ? std::to_string(ps.d.ny).c_str() : "", ps.d.rank == 3 ? "," : "",
                 ps.d.rank == 3 ? std::to_string(ps.d.nz).c_str() : "", (long long)ps.d.batch, ps.d.dir,
@@ -494,7 +509,7 @@ std::string describe(const PlanSpec& ps) {
                 ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
                 ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
-                ps.tuned_us, ps.d.nshards, ps.d.shard, (long long)ps.shard_n1);
+                ps.tuned_us, ps.d.nshards, ps.d.shard, (long long)ps.shard_n1, (long long)ps.npts);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
@@ -517,14 +532,21 @@ std::string describe(const PlanSpec& ps) {
     std::snprintf(b, sizeof b,
                   "%s{\"kernel\":\"%s\",\"L\":%d,\"radices\":%s,\"C\":%d,\"NT\":%d,\"grid\":%lld,"
                   "\"lds\":%zu,\"xtw\":%d,\"tstore\":%d,\"scale\":%d,\"src\":%d,\"dst\":%d,"
-                  "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld,\"real\":%d}",
+                  "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld,\"real\":%d,\"blocks\":%lld,"
+                  "\"in_outer\":%lld,\"out_outer\":%lld,\"q\":%lld,\"qstride\":%lld,"
+                  "\"xdiv\":%lld,\"xoff\":%lld,\"tblk\":%lld,\"tblk_stride\":%lld,\"lines\":%lld,"
+                  "\"tpb\":%lld}",
                   i ? "," : "",
                   p.key.kind == K_ROW ? "row"
                   : p.key.kind == K_BIG ? "big"
                   : p.key.kind == K_PLANE ? "plane" : "col",
                   p.key.L, rad.c_str(), p.key.C,
                   p.key.NT, (long long)p.grid, p.lds, p.key.xtw, p.key.tstore, p.scale, p.src,
-                  p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod, p.key.real);
+                  p.dst, (long long)p.s_in, (long long)p.s_out, (long long)p.xmod, p.key.real,
+                  (long long)p.blocks, (long long)p.in_outer, (long long)p.out_outer, (long long)p.q,
+                  (long long)p.qstride, (long long)p.xdiv, (long long)p.xoff,
+                  (long long)(p.tblk > 0 ? p.tblk : p.key.L), (long long)p.tblk_stride,
+                  (long long)p.ntrans, (long long)p.tpb);
     s += b;
   }
   s += "]}";
@@ -548,6 +570,7 @@ struct DevPass {
   float2* tw = nullptr;      // W_L^m
   float2* xtw_lo = nullptr;  // two-level W_M tables
   float2* xtw_hi = nullptr;
+  void* fimg2 = nullptr;     // A_k images of the matrix-core radix-R0 block (R0 = 2, 4)
   int xbits = 0;
   int persist_grid = 0;      // resident workgroups for the grouped (persistent) launch
   int single_grid = 0;       // resident workgroups of the single kernel (persistent variants)
@@ -672,6 +695,12 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
         dpp.single_grid = per_cu * ncu;
       }
       void* t = nullptr;
+      const int r0 = r0_of(sp.key.L);
+      if (r0 == 2 || r0 == 4) {
+        if ((st = dev_alloc(p, (size_t)r0 * 256 * 16, &dpp.fimg2))) break;
+        // both stages' scales: 2^-1 (radix 2 or 4) and 2^-2 (radix 16)
+        launch_gen_fimg_r(dpp.fimg2, r0, sgn, noscale ? 1.0 : 0.125, s);
+      }
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
       launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
@@ -746,6 +775,7 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   }
   kp.tw = dpp.tw;
   kp.fimg = p->fimg;
+  kp.fimg2 = dpp.fimg2;
   kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
   kp.r0scale2 = 1.0f;
   if (sp.key.kind == K_PLANE) {  // rows of nz, then columns of ny, each with its own radix-R0 scale
@@ -1225,7 +1255,8 @@ std::vector<Choice> candidates_base(const Desc& d) {
       }
     }
   }
-  if (lg > 22) {  // three passes
+  if (lg >= 20) {  // three passes (above 2^22 the only split; from 2^20 an
+                   // alternative whose short passes take wide column blocks)
     std::vector<int> base = long_split(d.nx);
     if (base.size() == 2) {  // a balanced three-way split as an extra candidate
       base = {1 << (lg / 3), 1 << ((lg - lg / 3) / 2), 1 << (lg - lg / 3 - (lg - lg / 3) / 2)};
@@ -1382,7 +1413,9 @@ tcfft_status create_impl(const Desc& d, tcfft_plan* out) {
   if ((st = build_spec(d, ch, &ps))) return st;
   ps.tuned = tuned;
   ps.tuned_us = tuned_us;
-  return create_device_plan(ps, out);
+  st = create_device_plan(ps, out);
+  if (!st && log_on()) std::fprintf(stderr, "tcfft: plan %s\n", describe(ps).c_str());
+  return st;
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -1420,9 +1453,9 @@ tcfft_status tcfft_plan_create(tcfft_plan* out, int rank, const int64_t* dims, i
   d.prec = precision;
   d.flags = flags;
   try {
-    return create_impl(d, out);
+    return logged(create_impl(d, out), "tcfft_plan_create");
   } catch (...) {
-    return TCFFT_ERR_INTERNAL;
+    return logged(TCFFT_ERR_INTERNAL, "tcfft_plan_create");
   }
 }
 
@@ -1437,10 +1470,14 @@ tcfft_status tcfft_plan_2d(tcfft_plan* out, int64_t nx, int64_t ny, int64_t batc
 }
 
 tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream) {
-  if (!plan || !in || !out) return TCFFT_ERR_INVALID_ARG;
-  if (!aligned16(in) || !aligned16(out) || real_overlap(plan, in, out)) return TCFFT_ERR_INVALID_ARG;
-  if (plan->spec.d.nshards > 0) return TCFFT_ERR_UNSUPPORTED;  // two steps around an exchange
-  return exec_any(plan, in, out, (hipStream_t)stream);
+  tcfft_status st = TCFFT_OK;
+  if (!plan || !in || !out || !aligned16(in) || !aligned16(out) || real_overlap(plan, in, out))
+    st = TCFFT_ERR_INVALID_ARG;
+  else if (plan->spec.d.nshards > 0)
+    st = TCFFT_ERR_UNSUPPORTED;  // two steps around an exchange
+  else
+    st = exec_any(plan, in, out, (hipStream_t)stream);
+  return logged(st, "tcfft_exec");
 }
 
 tcfft_status tcfft_plan_create_shard(tcfft_plan* out, int64_t n, int64_t batch, int dir,
@@ -1457,7 +1494,7 @@ tcfft_status tcfft_plan_create_shard(tcfft_plan* out, int64_t n, int64_t batch, 
   d.nshards = nshards;
   d.shard = shard;
   try {
-    return create_impl(d, out);
+    return logged(create_impl(d, out), "tcfft_plan_create_shard");
   } catch (...) {
     return TCFFT_ERR_INTERNAL;
   }
@@ -1493,13 +1530,17 @@ tcfft_status tcfft_exec_shard(tcfft_plan plan, int step, const void* in, void* o
 
 tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int npasses,
                                void* stream) {
-  if (!plan || !in || !out || in == out) return TCFFT_ERR_INVALID_ARG;
-  if (!aligned16(in) || !aligned16(out)) return TCFFT_ERR_INVALID_ARG;
-  if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0 ||
-      plan->spec.d.nshards > 0)
-    return TCFFT_ERR_UNSUPPORTED;
-  if (npasses < 1 || npasses > (int)plan->dp.size()) return TCFFT_ERR_INVALID_ARG;
-  return exec_impl(plan, in, out, (hipStream_t)stream, npasses);
+  tcfft_status st = TCFFT_OK;
+  if (!plan || !in || !out || in == out || !aligned16(in) || !aligned16(out))
+    st = TCFFT_ERR_INVALID_ARG;
+  else if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0 ||
+           plan->spec.d.nshards > 0)
+    st = TCFFT_ERR_UNSUPPORTED;
+  else if (npasses < 1 || npasses > (int)plan->dp.size())
+    st = TCFFT_ERR_INVALID_ARG;
+  else
+    st = exec_impl(plan, in, out, (hipStream_t)stream, npasses);
+  return logged(st, "tcfft_exec_passes");
 }
 
 }  // extern "C"
@@ -1529,9 +1570,9 @@ extern "C" {
 tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, void* const* out,
                              int njobs, void* stream) {
   tcfft_status st = check_many(plans, in, out, njobs);
-  if (st || njobs == 0) return st;
+  if (st || njobs == 0) return logged(st, "tcfft_exec_many");
   try {
-    return exec_many_impl(plans, in, out, njobs, (hipStream_t)stream);
+    return logged(exec_many_impl(plans, in, out, njobs, (hipStream_t)stream), "tcfft_exec_many");
   } catch (...) {
     return TCFFT_ERR_INTERNAL;
   }
@@ -1656,7 +1697,10 @@ void tcfft_tune_cache_clear(void) {
 }
 
 const char* tcfft_status_string(tcfft_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the value without an enum-typed load
+  int v = 0;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case TCFFT_OK: return "ok";
     case TCFFT_ERR_INVALID_ARG: return "invalid argument";
     case TCFFT_ERR_UNSUPPORTED: return "unsupported size or configuration";
@@ -1664,6 +1708,8 @@ const char* tcfft_status_string(tcfft_status s) {
     case TCFFT_ERR_ALLOC: return "device allocation failed";
     case TCFFT_ERR_LAUNCH: return "kernel launch failed";
     case TCFFT_ERR_INTERNAL: return "internal error";
+    case TCFFT_ERR_TIMEOUT: return "timed out in the queue";
+    case TCFFT_ERR_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }

@@ -21,7 +21,8 @@ lib = _tc.lib
 class ServerConfig(ctypes.Structure):
     _fields_ = [("nslots", ctypes.c_int), ("max_batch_jobs", ctypes.c_int),
                 ("mem_budget_bytes", ctypes.c_size_t), ("arena_bytes", ctypes.c_size_t),
-                ("use_graphs", ctypes.c_int), ("batch_window_us", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("batch_window_us", ctypes.c_int),
+                ("queue_timeout_us", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -50,6 +51,8 @@ lib.tcfft_server_poll.argtypes = [ctypes.c_void_p, _P(Completion), ctypes.c_int]
 lib.tcfft_server_wait_idle.argtypes = [ctypes.c_void_p, ctypes.c_int64]
 lib.tcfft_server_get_stats.argtypes = [ctypes.c_void_p, _P(ServerStats)]
 lib.tcfft_server_destroy.argtypes = [ctypes.c_void_p]
+lib.tcfft_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+lib.tcfft_server_cancel.restype = ctypes.c_int
 lib.tcfft_server_now_ns.argtypes = []
 lib.tcfft_server_now_ns.restype = ctypes.c_int64
 for _f in ("tcfft_server_create", "tcfft_server_prepare", "tcfft_server_submit", "tcfft_server_poll",
@@ -77,12 +80,13 @@ def _request(rank, dims, batch, direction, precision, in_ptr=0, out_ptr=0, tag=0
 
 class Server:
     def __init__(self, nslots: int = 4, mem_budget_bytes: int = 16 << 30, max_batch_jobs: int = 256,
-                 arena_bytes: int = 0, use_graphs: bool = False, batch_window_us: int = 0):
+                 arena_bytes: int = 0, use_graphs: bool = False, batch_window_us: int = 0,
+                 queue_timeout_us: int = 0):
         """Defaults favour latency: immediate dispatch with direct grouped
         launches.  At batches of a few jobs, graph replay and a batching window
         add more latency than they save launch work."""
         cfg = ServerConfig(nslots, max_batch_jobs, mem_budget_bytes, arena_bytes, int(use_graphs),
-                           int(batch_window_us))
+                           int(batch_window_us), int(queue_timeout_us))
         h = ctypes.c_void_p()
         st = lib.tcfft_server_create(ctypes.byref(h), ctypes.byref(cfg))
         if st != 0:
@@ -101,6 +105,13 @@ class Server:
     def submit(self, rank, dims, batch, direction, precision, in_ptr, out_ptr, tag) -> int:
         r = _request(rank, dims, batch, direction, precision, in_ptr, out_ptr, tag)
         return int(lib.tcfft_server_submit(self._h, ctypes.byref(r)))
+
+    def cancel(self, tag: int) -> int:
+        """Cancels the queued (not yet launched) requests with this tag."""
+        n = lib.tcfft_server_cancel(self._h, int(tag))
+        if n < 0:
+            raise _tc.TcfftError(-n, "tcfft_server_cancel")
+        return int(n)
 
     def poll(self) -> list:
         out = []

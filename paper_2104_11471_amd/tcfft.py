@@ -27,7 +27,7 @@ _PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_F
          "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "alloc",
-          5: "launch", 6: "internal"}
+          5: "launch", 6: "internal", 7: "timeout", 8: "cancelled"}
 
 # every symbol include/tcfft.h declares
 EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", "tcfft_exec_many",
@@ -39,7 +39,8 @@ EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", 
            "tcfft_tune_cache_clear", "tcfft_server_create", "tcfft_server_prepare",
            "tcfft_server_submit", "tcfft_server_poll", "tcfft_server_wait_idle",
            "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns",
-           "tcfft_plan_create_shard", "tcfft_exec_shard", "tcfft_shard_dry_run"]
+           "tcfft_plan_create_shard", "tcfft_exec_shard", "tcfft_shard_dry_run",
+           "tcfft_server_cancel"]
 
 
 class TcfftError(RuntimeError):
