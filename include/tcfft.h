@@ -152,6 +152,25 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
                              int njobs, void* stream);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): tcfft_exec_many with its
+ * descriptor tables in a static device array of TCFFT_STATIC_SCRATCH_BYTES
+ * per GPU (held until the process ends) instead of a stream-ordered
+ * allocation, written by kernels from their arguments instead of a copy from
+ * pinned host memory.  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Same jobs, rules and results as tcfft_exec_many (bitwise equal);
+ * every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (different streams, no ordering between them) race; calls on one stream
+ * are ordered.  Plans must be created beforehand (plan creation allocates).
+ * Errors: as tcfft_exec_many; INVALID_ARG for njobs > TCFFT_STATIC_MAX_JOBS;
+ * NO_DEVICE when the array's address cannot be taken.
+ */
+#define TCFFT_STATIC_SCRATCH_BYTES (1u << 20)
+#define TCFFT_STATIC_MAX_JOBS 1024
+tcfft_status tcfft_exec_many_static(const tcfft_plan* plans, const void* const* in,
+                                    void* const* out, int njobs, void* stream);
+
+/*
  * Runs only the first `npasses` passes of a multi-pass FP16 or split plan and
  * writes that pass's result to `out` (used to check the intermediate against
  * the decomposition of Sec. 2.1, Eq. 3).  After pass 1 of a long 1D plan with

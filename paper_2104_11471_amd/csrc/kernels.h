@@ -127,4 +127,11 @@ void launch_r2c_post(const void* z, void* x, const float2* tw, int64_t M, int64_
 void launch_c2r_pre(const void* x, void* z, const float2* tw, int64_t M, int64_t batch,
                     bool split, hipStream_t s);
 
+// Allocation-free execution (k_static.hip): the current device's copy of the
+// static descriptor scratch array (address taken once per device) and its
+// size; a device write of `bytes` (a multiple of 4) from host memory carried
+// in kernel arguments, stream-ordered, with no staging allocation.
+hipError_t static_scratch(void** out, size_t* bytes);
+hipError_t launch_write_words(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace tcfft

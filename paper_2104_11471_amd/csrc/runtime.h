@@ -39,9 +39,11 @@ struct GraphCache {
 // descriptor tables go there instead of a stream-ordered allocation; with
 // graphs as well, the launch sequence is captured once per variant sequence
 // and replayed as a HIP graph.
+// arg_upload: the tables are written by kernels from their arguments instead
+// of a copy from pinned host memory (no host or device allocation).
 tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s,
                                       void* desc_arena, size_t arena_cap,
-                                      tcfft::GraphCache* graphs);
+                                      tcfft::GraphCache* graphs, bool arg_upload = false);
 // Descriptor arena bytes that always suffice for a batch of max_jobs jobs.
 size_t tcfft_internal_desc_bytes(int max_jobs);
 size_t tcfft_internal_plan_ws_bytes(const tcfft_plan_s* p, int64_t batch);

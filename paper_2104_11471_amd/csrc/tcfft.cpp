@@ -998,7 +998,7 @@ tcfft::GraphCache::~GraphCache() {
 
 tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s,
                                       void* desc_arena, size_t arena_cap,
-                                      tcfft::GraphCache* graphs) {
+                                      tcfft::GraphCache* graphs, bool arg_upload) {
   int levels = 0;
   for (int j = 0; j < njobs; ++j) {
     tcfft_plan_s* p = jobs[j].plan;
@@ -1064,8 +1064,12 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     std::memcpy(host.data() + off[i] + jb, groups[i].prefix.data(),
                 groups[i].prefix.size() * sizeof(int64_t));
   }
-  tcfft_status st = upload(dmem, host.data(), total_bytes, s);
-  if (st) return st;
+  tcfft_status st = TCFFT_OK;
+  if (arg_upload) {
+    if (launch_write_words(dmem, host.data(), total_bytes, s) != hipSuccess) return TCFFT_ERR_LAUNCH;
+  } else if ((st = upload(dmem, host.data(), total_bytes, s))) {
+    return st;
+  }
   auto launch_all = [&](bool full_grid) -> tcfft_status {
     for (size_t i = 0; i < G; ++i) {
       const Group& g = groups[i];
@@ -1135,7 +1139,7 @@ int tcfft_internal_plan_prec(const tcfft_plan_s* p) { return p->spec.d.prec; }
 namespace {
 
 tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void* const* out,
-                            int njobs, hipStream_t s) {
+                            int njobs, hipStream_t s, bool use_static = false) {
   std::vector<Job> jobs;
   std::vector<int> post;  // real forward jobs: their spectrum pass runs after the group
   jobs.reserve(njobs);
@@ -1162,7 +1166,14 @@ tcfft_status exec_many_impl(const tcfft_plan* plans, const void* const* in, void
     jobs.push_back(Job{p, ji, jo, ps.d.batch, p->ws});
   }
   if (!jobs.empty()) {
-    tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), s, nullptr, 0, nullptr);
+    void* arena = nullptr;
+    size_t cap = 0;
+    if (use_static && static_scratch(&arena, &cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_NO_DEVICE;
+    }
+    tcfft_status st = tcfft_internal_exec_jobs(jobs.data(), (int)jobs.size(), s, arena, cap,
+                                               nullptr, use_static);
     if (st) return st;
   }
   for (int j : post) launch_real_step(plans[j], nullptr, out[j], s);
@@ -1573,6 +1584,19 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
   if (st || njobs == 0) return logged(st, "tcfft_exec_many");
   try {
     return logged(exec_many_impl(plans, in, out, njobs, (hipStream_t)stream), "tcfft_exec_many");
+  } catch (...) {
+    return TCFFT_ERR_INTERNAL;
+  }
+}
+
+tcfft_status tcfft_exec_many_static(const tcfft_plan* plans, const void* const* in,
+                                    void* const* out, int njobs, void* stream) {
+  if (njobs > TCFFT_STATIC_MAX_JOBS) return TCFFT_ERR_INVALID_ARG;
+  tcfft_status st = check_many(plans, in, out, njobs);
+  if (st || njobs == 0) return st;
+  try {
+    return logged(exec_many_impl(plans, in, out, njobs, (hipStream_t)stream, true),
+                  "tcfft_exec_many_static");
   } catch (...) {
     return TCFFT_ERR_INTERNAL;
   }

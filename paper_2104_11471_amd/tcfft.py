@@ -40,7 +40,7 @@ EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", 
            "tcfft_server_submit", "tcfft_server_poll", "tcfft_server_wait_idle",
            "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns",
            "tcfft_plan_create_shard", "tcfft_exec_shard", "tcfft_shard_dry_run",
-           "tcfft_server_cancel"]
+           "tcfft_exec_many_static", "tcfft_server_cancel"]
 
 
 class TcfftError(RuntimeError):
@@ -70,6 +70,8 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_plan_2d.argtypes = [P(vp), i64, i64, i64]
     lib.tcfft_exec.argtypes = [vp, vp, vp, vp]
     lib.tcfft_exec_many.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
+    lib.tcfft_exec_many_static.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
+    lib.tcfft_exec_many_static.restype = ctypes.c_int
     lib.tcfft_exec_passes.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.tcfft_plan_destroy.argtypes = [vp]
     lib.tcfft_plan_scale_log2.argtypes = [vp]
@@ -320,8 +322,12 @@ class Plan:
             pass
 
 
-def exec_many(plans, xs, outs, stream=None) -> None:
-    """Runs plans[j] on (xs[j], outs[j]) for all j in one call."""
+STATIC_MAX_JOBS = 1024
+
+
+def exec_many(plans, xs, outs, stream=None, static: bool = False) -> None:
+    """Runs plans[j] on (xs[j], outs[j]) for all j in one call
+    (tcfft_exec_many, or tcfft_exec_many_static with ``static``)."""
     import torch
     n = len(plans)
     VP = ctypes.c_void_p
@@ -332,9 +338,10 @@ def exec_many(plans, xs, outs, stream=None) -> None:
         p._check(x, "input")
         p._check(o, "output")
     s = stream if stream is not None else torch.cuda.current_stream()
-    st = lib.tcfft_exec_many(hp, ip, op, n, VP(s.cuda_stream))
+    fn = lib.tcfft_exec_many_static if static else lib.tcfft_exec_many
+    st = fn(hp, ip, op, n, VP(s.cuda_stream))
     if st != 0:
-        raise TcfftError(st, "tcfft_exec_many")
+        raise TcfftError(st, "tcfft_exec_many_static" if static else "tcfft_exec_many")
 
 
 def shard_dry_run(n: int, batch: int, nshards: int, shard: int, direction: int = FORWARD,
