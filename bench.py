@@ -93,7 +93,9 @@ def kernel_name(q: dict) -> str:
     """Template name of a pass's kernel from the plan description."""
     r0 = q["radices"][0] if q["radices"][0] != 16 else 1
     if q["kernel"] == "row":
-        return f"row_kernel<{q['L']}, {r0}, {q['NT']}, false, {str(bool(q['tstore'])).lower()}, {q['real']}>"
+        wgp = q["C"] if q["C"] else 16384  # points per workgroup
+        return (f"row_kernel<{q['L']}, {r0}, {q['NT']}, false, {str(bool(q['tstore'])).lower()}, "
+                f"{q['real']}, {wgp}>")
     if q["kernel"] == "col":
         return (f"col_kernel<{q['L']}, {r0}, {q['C']}, {q['NT']}, false, "
                 f"{str(bool(q['xtw'])).lower()}, {str(bool(q['tstore'])).lower()}>")

@@ -53,18 +53,20 @@ void launch_gen_twiddles(float2* tw, int64_t count, int64_t modulus, int64_t mul
 }
 
 // Lane = 16 g + m holds row m of the A operand, K entries of input rows
-// r = 4g..4g+3; entry (m, r) = F_16[m][r] W_{16 R}^{k r} = W_{16 R}^{r (R m + k)}
-// (R = 1, k = 0: the plain radix-16 matrix).
-__global__ void gen_fimg_kernel(h8* img, double sgn, double scale, int R, int k) {
+// r = 4g..4g+3.  Entry (m, r) is F_16[m][r] W_{16 R}^{k r} = W_{16 R}^{r (R m + k)}
+// (an input twiddle; R = 1, k = 0: the plain radix-16 matrix), or with P > 0
+// W_{16 P}^{m lo} F_16[m][r] = W_{16 P}^{m (P r + lo)} (an output twiddle).
+__global__ void gen_fimg_kernel(h8* img, double sgn, double scale, int R, int k, int P, int lo) {
   const int lane = threadIdx.x;  // 64 lanes
   const int g = lane >> 4, m = lane & 15;
   h8 rh, ih, rl, il;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = 4 * g + i;
-    const int e = (r * (R * m + k)) % (16 * R);
+    const int mod = 16 * (P > 0 ? P : R);
+    const int e = P > 0 ? (m * (P * r + lo)) % mod : (r * (R * m + k)) % mod;
     double sn, cs;
-    sincospi(2.0 * (double)e / (16.0 * R), &sn, &cs);
+    sincospi(2.0 * (double)e / (double)mod, &sn, &cs);
     const double fr = cs * scale, fi = sgn * sn * scale;
     // Yr row: [Fr, -Fi]; Yi row: [Fi, Fr]  (pairs = re/im halves of input row r)
     const double vr[2] = {fr, -fi}, vi[2] = {fi, fr};
@@ -86,7 +88,7 @@ __global__ void gen_fimg_kernel(h8* img, double sgn, double scale, int R, int k)
 
 void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s) {
   hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<h8*>(img), sgn,
-                     scale, 1, 0);
+                     scale, 1, 0, 0, 0);
 }
 
 void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s) {
@@ -95,8 +97,14 @@ void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s
     // follow the forward sign, whose W^{k' d} is the inverse W^{k d})
     const int k = sgn > 0 ? (R - slot) % R : slot;
     hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s,
-                       reinterpret_cast<h8*>(img) + 256 * slot, sgn, scale, R, k);
+                       reinterpret_cast<h8*>(img) + 256 * slot, sgn, scale, R, k, 0, 0);
   }
+}
+
+void launch_gen_fimg_tw(void* img, int P, double sgn, double scale, hipStream_t s) {
+  for (int lo = 0; lo < P; ++lo)
+    hipLaunchKernelGGL(gen_fimg_kernel, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<h8*>(img) + 256 * lo, sgn, scale, 1, 0, P, lo);
 }
 
 // Autotuner scratch data: FP16 complex words with re, im in [-1, 1) from a

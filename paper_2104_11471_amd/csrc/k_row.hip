@@ -4,7 +4,8 @@
 namespace tcfft {
 
 #define ROWK(L_, R_, N_)                                                             \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore && !k.real) {\
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore && !k.real &&  \
+      k.C == 0) {                                                                    \
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true>;                          \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true>;                      \
@@ -17,9 +18,25 @@ namespace tcfft {
     return true;                                                                     \
   }
 
+// 8192 points per workgroup (KernelKey.C = 8192; FP16 and split, 256 threads).
+#define ROWKH(L_, R_)                                                                \
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == 256 && k.C == 8192 &&     \
+      !k.tstore && !k.real) {                                                        \
+    if (k.split) {                                                                   \
+      out->single = (KernelFn)row_kernel<L_, R_, 256, true, false, 0, 8192>;         \
+      out->multi = (MultiFn)row_kernel_multi<L_, R_, 256, true, false, 0, 8192>;     \
+    } else {                                                                        \
+      out->single = (KernelFn)row_kernel<L_, R_, 256, false, false, 0, 8192>;        \
+      out->multi = (MultiFn)row_kernel_multi<L_, R_, 256, false, false, 0, 8192>;    \
+    }                                                                                \
+    out->persistent = false;                                                         \
+    return true;                                                                     \
+  }
+
 // Transposed-store variants (second pass of a four-step transform).
 #define ROWKT(L_, R_, N_)                                                            \
-  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && k.tstore && !k.real) {\
+  if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && k.tstore && !k.real &&   \
+      k.C == 0) {                                                                    \
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true, true>;                    \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true, true>;                \
@@ -61,6 +78,12 @@ bool find_row_kernels(const KernelKey& k, KernelFns* out) {
   ROWK(16384, 4, 256)
   ROWK(8192, 2, 512)
   ROWK(16384, 4, 512)
+  ROWKH(256, 1)
+  ROWKH(512, 2)
+  ROWKH(1024, 4)
+  ROWKH(2048, 8)
+  ROWKH(4096, 1)
+  ROWKH(8192, 2)
   ROWKT(256, 1, 256)
   ROWKT(512, 2, 256)
   ROWKT(1024, 4, 256)

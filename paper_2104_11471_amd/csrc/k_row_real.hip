@@ -7,7 +7,7 @@ namespace tcfft {
 
 #define ROWKR1(L_, R_, N_, RK_)                                                      \
   if (k.kind == K_ROW && k.L == L_ && k.R0 == R_ && k.NT == N_ && !k.tstore &&       \
-      k.real == RK_) {                                                               \
+      k.real == RK_ && k.C == 0) {                                                   \
     if (k.split) {                                                                   \
       out->single = (KernelFn)row_kernel<L_, R_, N_, true, false, RK_>;              \
       out->multi = (MultiFn)row_kernel_multi<L_, R_, N_, true, false, RK_>;          \

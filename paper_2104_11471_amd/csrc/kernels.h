@@ -43,12 +43,15 @@ struct KParams {
   // A operands of the matrix-core radix-R0 x radix-16 block (R0 images A_k,
   // 256 h8 each: Yr-hi, Yi-hi, Yr-lo, Yi-lo), pass-specific
   const void* fimg2;
+  // A operands of the radix-16 LDS stage of digit stride 16 with its twiddle
+  // folded in (16 images A_lo, 256 h8 each), pass-specific
+  const void* fimg3;
 };
 
 // The same struct is read by host code (x86-64) and, in grouped launches, by
 // device code from a table in device memory: both ABIs lay it out alike
 // (8-byte pointers and int64_t, 4-byte float/int32, natural alignment).
-static_assert(sizeof(KParams) == 200, "KParams layout changed: host and device must agree");
+static_assert(sizeof(KParams) == 208, "KParams layout changed: host and device must agree");
 
 // Kernel variants.  `kind` selects the family, the rest are the template
 // parameters of that family (see kernels.hip).
@@ -116,6 +119,9 @@ void launch_gen_fimg(void* img, double sgn, double scale, hipStream_t s);
 // img + 256 k (h8 units; inverse sgn: slot k' holds k = (R - k') mod R), the
 // same four images as launch_gen_fimg.
 void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s);
+// A_lo = diag(W_{16 P}^{k1 lo}) . F_16 scaled by `scale`, for lo = 0..P-1, at
+// img + 256 lo (h8 units), the same four images as launch_gen_fimg.
+void launch_gen_fimg_tw(void* img, int P, double sgn, double scale, hipStream_t s);
 void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s);
 
 // Real-input transforms around an M-point complex transform (N = 2M reals).

@@ -59,6 +59,16 @@ __device__ __forceinline__ u4 gld4(const uint32_t* ptr) {
   return *(const TCFFT_GLOBAL u4*)(ptr);
 }
 __device__ __forceinline__ void gst4(uint32_t* ptr, u4 v) { *(TCFFT_GLOBAL u4*)(ptr) = v; }
+// Row passes stream their lines through once with non-temporal accesses
+// (measured faster for contiguous 16-byte-per-lane lines; column passes, whose
+// rows are 64-256-byte runs, keep the default cache policy, which measured
+// faster for them).
+__device__ __forceinline__ u4 rld4(const uint32_t* ptr) {
+  return __builtin_nontemporal_load((const TCFFT_GLOBAL u4*)(ptr));
+}
+__device__ __forceinline__ void rst4(uint32_t* ptr, u4 v) {
+  __builtin_nontemporal_store(v, (TCFFT_GLOBAL u4*)(ptr));
+}
 __device__ __forceinline__ uint32_t gld1(const uint32_t* ptr) {
   return *(const TCFFT_GLOBAL uint32_t*)(ptr);
 }
@@ -139,12 +149,15 @@ __device__ __forceinline__ float2 value(uint32_t h, uint32_t l) {
 // ===========================================================================
 // Row kernel: TPB contiguous lines per workgroup, LDS position p = tau*L + j.
 // ===========================================================================
-template <int L_, int R0_, int NT_>
+template <int L_, int R0_, int NT_, int WGP_ = 16384>
 struct RowGeom {
   static constexpr int L = L_, R0 = R0_, NT = NT_;
   static constexpr int S = (ilog2c(L) - ilog2c(R0)) / 4;
   static_assert(pow16(S) * R0 == L, "L must be R0 * 16^S");
-  static constexpr int WGPTS = 16384;  // points per workgroup (4 quads per wave at 256 threads)
+  // points per workgroup: 16384 = 4 quads per wave at 256 threads (64 KB of
+  // FP16 LDS, two workgroups per CU); 8192 halves the LDS and the registers a
+  // lane holds, for more resident waves
+  static constexpr int WGPTS = WGP_;
   static constexpr int TPB = L >= WGPTS ? 1 : WGPTS / L;
   static constexpr int PTS = TPB * L;
   static constexpr int NW = NT / 64;
@@ -215,8 +228,8 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
         if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, p);
         else ll[d] = u4{0, 0, 0, 0};
       } else {
-        hh[d] = gld4(kp.in + g0 + p);
-        if constexpr (SPLIT) ll[d] = gld4(kp.in + kp.in_plane + g0 + p);
+        hh[d] = rld4(kp.in + g0 + p);
+        if constexpr (SPLIT) ll[d] = rld4(kp.in + kp.in_plane + g0 + p);
         else ll[d] = u4{0, 0, 0, 0};
       }
     }
@@ -283,8 +296,8 @@ __device__ __forceinline__ void row_stage16_load(const KParams& kp, int valid, i
     for (int i = 0; i < 4; ++i) {
       int p = row_pos_t<L, P>(col0, 4 * g + i);
       if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
-      r.h[qq][i] = gld4(kp.in + g0 + p);
-      if constexpr (SPLIT) r.l[qq][i] = gld4(kp.in + kp.in_plane + g0 + p);
+      r.h[qq][i] = rld4(kp.in + g0 + p);
+      if constexpr (SPLIT) r.l[qq][i] = rld4(kp.in + kp.in_plane + g0 + p);
       else r.l[qq][i] = u4{0, 0, 0, 0};
     }
   }
@@ -333,8 +346,8 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
           rl[i] = pre->l[qq][i];
         } else if constexpr (SRCG) {
           if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
-          rh[i] = gld4(kp.in + g0 + p);
-          if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + g0 + p);
+          rh[i] = rld4(kp.in + g0 + p);
+          if constexpr (SPLIT) rl[i] = rld4(kp.in + kp.in_plane + g0 + p);
         } else {
           rh[i] = lds_ld4(lds, p);
           if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, p);
@@ -358,8 +371,8 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
         if constexpr (SRCG && G::TPB > 1) tau = tau < valid ? tau : 0;
         const int p = tau * L + posrev_hi<R0, S>(TT ? klowT : col % (L / 16)) * 16 + 4 * g;
         if constexpr (SRCG) {
-          xh[t] = gld4(kp.in + g0 + p);
-          if constexpr (SPLIT) xl[t] = gld4(kp.in + kp.in_plane + g0 + p);
+          xh[t] = rld4(kp.in + g0 + p);
+          if constexpr (SPLIT) xl[t] = rld4(kp.in + kp.in_plane + g0 + p);
         } else {
           xh[t] = lds_ld4(lds, p);
           if constexpr (SPLIT) xl[t] = lds_ld4(ldsl, p);
@@ -411,9 +424,9 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
         for (int j = 0; j < 4; ++j) {
           const int64_t o = base + (int64_t)(klowT + (L / 16) * (4 * g + j)) * kp.s_out;
           if (tau0 + 3 < valid) {
-            gst4(kp.out + o, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+            rst4(kp.out + o, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
             if constexpr (SPLIT)
-              gst4(kp.out + kp.out_plane + o, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
+              rst4(kp.out + kp.out_plane + o, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
           } else {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
@@ -430,9 +443,9 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int64_t o = g0 + (int64_t)tau * L + klow0 + (L / 16) * (4 * g + j);
-            gst4(kp.out + o, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+            rst4(kp.out + o, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
             if constexpr (SPLIT)
-              gst4(kp.out + kp.out_plane + o, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
+              rst4(kp.out + kp.out_plane + o, u4{ol[0][j], ol[1][j], ol[2][j], ol[3][j]});
           }
         }
       } else if constexpr (L == 16) {
@@ -441,9 +454,9 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
           const int tau = col0 + t;
           if (tau < valid) {
             const int64_t o = g0 + (int64_t)tau * 16 + 4 * g;
-            gst4(kp.out + o, u4{oh[t][0], oh[t][1], oh[t][2], oh[t][3]});
+            rst4(kp.out + o, u4{oh[t][0], oh[t][1], oh[t][2], oh[t][3]});
             if constexpr (SPLIT)
-              gst4(kp.out + kp.out_plane + o, u4{ol[t][0], ol[t][1], ol[t][2], ol[t][3]});
+              rst4(kp.out + kp.out_plane + o, u4{ol[t][0], ol[t][1], ol[t][2], ol[t][3]});
           }
         }
       } else {
@@ -540,8 +553,8 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
           if constexpr (SPLIT) ll[d][i] = lds_ld4(ldsl, p);
           else ll[d][i] = u4{0, 0, 0, 0};
         } else {
-          hh[d][i] = gld4(kp.in + g0 + p);
-          if constexpr (SPLIT) ll[d][i] = gld4(kp.in + kp.in_plane + g0 + p);
+          hh[d][i] = rld4(kp.in + g0 + p);
+          if constexpr (SPLIT) ll[d][i] = rld4(kp.in + kp.in_plane + g0 + p);
           else ll[d][i] = u4{0, 0, 0, 0};
         }
       }
@@ -604,12 +617,211 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
   }
 }
 
+// ---------------------------------------------------------------------------
+// Radix-R0 x radix-16 block entirely on the matrix core (FP16 data).  With the
+// digits n = d P0 + m P + lo of a line (P0 = 16 P) and the DIF order of the
+// fused stage, radix-R0 output k and radix-16 output k1 are
+//   Y[k][k1][lo] = W_L^{(k + R0 k1) lo} *
+//                  sum_d W_R0^{k d} sum_m (F_16[k1][m] W_{16 R0}^{k m}) x[d][m][lo]
+// (Eq. 3 applied twice: W_L^{k m P} = W_{16 R0}^{k m}).  The bracket is the
+// A operand A_k of a radix-16 product, one image per k (plan table kp.fimg2,
+// scaled by both stages' scales), and the radix-R0 sum over d accumulates R0
+// such products in the MFMA accumulator.  W_R0^{k d} in {1, i, -1, -i} (R0 <= 4)
+// multiplies A_k exactly: with the images (Yr, Yi) of A_k,
+//   i A_k -> (-Yi, Yr),   -A_k -> (-Yr, -Yi),   -i A_k -> (Yi, -Yr),
+// so the raw FP16 inputs are the B operands (no vector-ALU butterflies and no
+// rounding before the product) and the only twiddle, W_L^{(k + R0 k1) lo},
+// is applied once to the FP32 accumulator.  The code follows the forward
+// sign: an inverse transform's W^{k d} is the forward W^{k' d} with
+// k' = (R0 - k) mod R0, so slot k' of an inverse plan's table holds A_k and
+// the block computed as k' is stored and twiddled as output k.
+__device__ __forceinline__ h8 neg_h8(h8 a) {
+  u4 v = __builtin_bit_cast(u4, a);
+  v ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  return __builtin_bit_cast(h8, v);
+}
+
+// Images of one A_k and their negations.
+struct FOpsMx {
+  h8 r, i, nr, ni;
+};
+
+__device__ __forceinline__ FOpsMx load_fops_mx(const void* fimg2, int k) {
+  const TCFFT_GLOBAL h8* f = (const TCFFT_GLOBAL h8*)(fimg2);
+  const int lane = threadIdx.x & 63;
+  FOpsMx o;
+  o.r = f[256 * k + lane];
+  o.i = f[256 * k + 64 + lane];
+  o.nr = neg_h8(o.r);
+  o.ni = neg_h8(o.i);
+  return o;
+}
+
+// yr, yi += (W^{k d} A_k) . b, where the forward W^{k d} = e^{-2 pi i Q / 4}
+// is Q quarter turns.
+template <int Q>
+__device__ __forceinline__ void mfma_rot(const FOpsMx& f, u4 b, f4& yr, f4& yi) {
+  const h8 bh = __builtin_bit_cast(h8, b);
+  h8 ar, ai;
+  constexpr int qq = (4 - Q) & 3;  // in units of +i
+  if constexpr (qq == 0) {
+    ar = f.r;
+    ai = f.i;
+  } else if constexpr (qq == 1) {
+    ar = f.ni;
+    ai = f.r;
+  } else if constexpr (qq == 2) {
+    ar = f.nr;
+    ai = f.ni;
+  } else {
+    ar = f.i;
+    ai = f.nr;
+  }
+  yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar, bh, yr, 0, 0, 0);
+  yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai, bh, yi, 0, 0, 0);
+}
+
+// Used for the 16384-point pass (R0 = 4): the four-fold matrix-core work of the
+// radix-4 sum there replaces the heaviest vector-ALU stage of the library; for
+// shorter lines it measured no faster than the vector-ALU radix-R0 stage.
+template <class G>
+struct RowFusedMx {
+  static constexpr bool value = RowFused<G>::value && (G::R0 == 2 || G::R0 == 4) &&
+                                G::L >= 16384;
+};
+
+// Radix-R0 sum over d for output k of the fused block (compile-time k, d).
+template <int R0, int K, int D = 0>
+__device__ __forceinline__ void mfma_rsum(const FOpsMx& f, const u4 (&b)[R0], f4& yr, f4& yi) {
+  mfma_rot<((K * D) % R0) * (4 / R0)>(f, b[D], yr, yi);
+  if constexpr (D + 1 < R0) mfma_rsum<R0, K, D + 1>(f, b, yr, yi);
+}
+
+template <class G, int K = 0>
+__device__ __forceinline__ void row_fused_mx_k(const KParams& kp, uint32_t* lds,
+                                               const u4 (&hh)[G::R0][4], int tau, int lo0) {
+  constexpr int L = G::L, R0 = G::R0;
+  constexpr int P = RowFused<G>::P, P0 = 16 * P;
+  const int g = (threadIdx.x & 63) >> 4;
+  const int k = kp.sgn < 0.f ? K : (R0 - K) % R0;  // the output this block is
+  const FOpsMx fm = load_fops_mx(kp.fimg2, K);
+  float2 st[4];  // W_L^e, e = k + R0 (4g + j)
+#pragma unroll
+  for (int j = 0; j < 4; ++j) st[j] = tld(kp.tw, k + R0 * (4 * g + j));
+  uint32_t oh[4][4];  // [t][j]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    u4 b[R0];
+#pragma unroll
+    for (int d = 0; d < R0; ++d) b[d] = u4{hh[d][0][t], hh[d][1][t], hh[d][2][t], hh[d][3][t]};
+    f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    mfma_rsum<R0, K>(fm, b, yr, yi);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // W_L^{e (lo0 + t)} = W_L^{e lo0} (W_L^e)^t, e = k + R0 (4g + j)
+      float2 w = tld(kp.tw, (k + R0 * (4 * g + j)) * lo0);
+#pragma unroll
+      for (int u = 0; u < t; ++u) w = cmul(w, st[j]);
+      const float2 z = cmul(make_float2(yr[j], yi[j]), w);
+      oh[t][j] = pack(z.x, z.y);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = tau * L + k * P0 + (4 * g + j) * P + lo0;
+    lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+  }
+  if constexpr (K + 1 < R0) row_fused_mx_k<G, K + 1>(kp, lds, hh, tau, lo0);
+}
+
+template <class G, bool SRCL = false>
+__device__ __forceinline__ void row_stage_fused_mx(const KParams& kp, uint32_t* lds, int valid,
+                                                   int64_t g0) {
+  constexpr int L = G::L, R0 = G::R0;
+  using F = RowFused<G>;
+  constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+  for (int it = 0; it < ITF; ++it) {
+    const int sq = (wave * ITF + it) * 16 + c16;
+    const int tau = sq / (P / 4);
+    const int lo0 = 4 * (sq % (P / 4));
+    const int taul = (!SRCL && G::TPB > 1 && tau >= valid) ? 0 : tau;
+    u4 hh[R0][4];  // [d][row i]: 4 consecutive low indices lo0..lo0+3
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = taul * L + d * P0 + (4 * g + i) * P + lo0;
+        if constexpr (SRCL) hh[d][i] = lds_ld4(lds, p);
+        else hh[d][i] = rld4(kp.in + g0 + p);
+      }
+    row_fused_mx_k<G>(kp, lds, hh, tau, lo0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix-16 LDS stage with digit stride 16 and its twiddle folded into the
+// matrix-core operand (FP16 data).  Columns of the stage are (line, hi, lo),
+// lo < 16; its DIF twiddle W_256^{k1 lo} depends on the output row k1 and on
+// lo only, so an MFMA tile of 16 columns with one lo and 16 consecutive hi
+// takes A_lo = diag(W_256^{k1 lo}) F_16 (16 images, plan table kp.fimg3) and
+// needs no vector-ALU twiddle.  A lane's 4 tiles are lo0..lo0+3 (16-byte LDS
+// accesses along lo), wave w takes lo0 = 4w and its quads run over the
+// (line, hi-group) pairs, so it loads its 4 images once per stage.
+template <class G>
+struct RowFold {
+  static constexpr int NH = G::L / 256;  // hi values per line at stride 16
+  static constexpr bool value = G::L >= 4096 && G::NT == 256 && G::NW == 4 &&
+                                G::TPB * NH / 16 == G::QPW;
+};
+
+template <class G>
+__device__ __forceinline__ void row_stage16_fold(const KParams& kp, uint32_t* lds) {
+  constexpr int L = G::L, P = 16, NH = RowFold<G>::NH, HG = NH / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int lo0 = 4 * wave;
+  const TCFFT_GLOBAL h8* img = (const TCFFT_GLOBAL h8*)(kp.fimg3);
+  h8 ar[4], ai[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ar[t] = img[256 * (lo0 + t) + lane];
+    ai[t] = img[256 * (lo0 + t) + 64 + lane];
+  }
+#pragma unroll
+  for (int qq = 0; qq < G::QPW; ++qq) {
+    const int tau = qq / HG, hi = (qq % HG) * 16 + c16;
+    const int base = tau * L + hi * 16 * P + lo0;
+    u4 rh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rh[i] = lds_ld4(lds, base + (4 * g + i) * P);
+    uint32_t oh[4][4];  // [t][j]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const h8 bh = __builtin_bit_cast(h8, u4{rh[0][t], rh[1][t], rh[2][t], rh[3][t]});
+      const f4 z = {0.f, 0.f, 0.f, 0.f};
+      const f4 yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar[t], bh, z, 0, 0, 0);
+      const f4 yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai[t], bh, z, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) oh[t][j] = pack(yr[j], yi[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      lds_st4(lds, base + (4 * g + j) * P, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+  }
+}
+
 template <class G, int E, bool SPLIT, bool TT = false, bool KEEP = false>
 __device__ __forceinline__ void row_stages_from(const KParams& kp, uint32_t* lds, int valid,
                                                 int64_t g0, const FOps& f) {
   // radix-16 stages with stride 16^E, 16^(E-1), ..., 1, all reading LDS
-  row_stage16<G, pow16(E), false, SPLIT, false, E == 0 && TT, E == 0 && KEEP>(kp, lds, valid, g0,
-                                                                              f);
+  if constexpr (E == 1 && !SPLIT && RowFold<G>::value)
+    row_stage16_fold<G>(kp, lds);
+  else
+    row_stage16<G, pow16(E), false, SPLIT, false, E == 0 && TT, E == 0 && KEEP>(kp, lds, valid,
+                                                                                g0, f);
   if constexpr (E > 0) {
     __syncthreads();
     row_stages_from<G, E - 1, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
@@ -795,9 +1007,9 @@ __device__ __forceinline__ void real_pre(const KParams& kp, uint32_t* lds, int v
 // One workgroup's share of a row pass: workgroup index wg of the pass.
 // RK: 0 complex; 1 real forward (spectrum epilogue); 2 real inverse (prologue);
 // 3 results stay in LDS in natural order (the first half of a plane pass).
-template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0, int WGP = 16384>
 __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
-  using G = RowGeom<L, R0, NT>;
+  using G = RowGeom<L, R0, NT, WGP>;
   static_assert(RK == 0 || (!TT && G::S >= 1 && L >= 64), "real / plane variants");
   constexpr bool KEEP = RK == 1 || RK == 3, SRCL = RK == 2;
   const int64_t t0 = wg * G::TPB;
@@ -809,7 +1021,11 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
     real_pre<G, SPLIT>(kp, lds, valid, t0);
     __syncthreads();
   }
-  if constexpr (RowFused<G>::value) {
+  if constexpr (!SPLIT && RowFusedMx<G>::value) {
+    row_stage_fused_mx<G, SRCL>(kp, lds, valid, g0);
+    __syncthreads();
+    row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
+  } else if constexpr (RowFused<G>::value) {
     row_stage_fused<G, SPLIT, SRCL>(kp, lds, valid, g0, f);
     __syncthreads();
     row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
@@ -874,13 +1090,13 @@ __device__ __forceinline__ void row_pipe(const KParams& kp, uint32_t* lds) {
   }
 }
 
-template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0, int WGP = 16384>
 __global__ __launch_bounds__(NT) void row_kernel(KParams kp) {
   extern __shared__ uint32_t lds[];
-  if constexpr (!TT && RK == 0 && RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
+  if constexpr (!TT && RK == 0 && WGP == 16384 && RowPipe<RowGeom<L, R0, NT>, SPLIT>::value)
     row_pipe<L, R0, NT, SPLIT>(kp, lds);
   else
-    row_body<L, R0, NT, SPLIT, TT, RK>(kp, blockIdx.x, lds);
+    row_body<L, R0, NT, SPLIT, TT, RK, WGP>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -1019,10 +1235,21 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
     // twiddles: the 4 tiles share (row, lo), hence one per row.  The extra
     // inter-pass twiddle W_M^{ci k} depends on the column ci too: with
     // ci = ci0 + t it is W_M^{ci0 k} * (W_M^k)^t (three lookups per row).
+    // FOLD (FP16, stride 16, 64 columns per quad): every column of the quad
+    // has the same lo, so the DIF twiddle W_256^{k1 lo} is folded into the
+    // matrix-core operand, A_lo = diag(W_256^{k1 lo}) F_16 (table kp.fimg3).
+    constexpr bool FOLD = !SPLIT && P == 16 && C >= 64;
+    h8 far, fai;
+    if constexpr (FOLD) {
+      const TCFFT_GLOBAL h8* img = (const TCFFT_GLOBAL h8*)(kp.fimg3);
+      far = img[256 * lo + lane];
+      fai = img[256 * lo + 64 + lane];
+    }
     float2 w[4][4];  // [t][j]
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if constexpr (P > 1) {
+      if constexpr (FOLD) {
+      } else if constexpr (P > 1) {
         const float2 v = tld(kp.tw, (4 * g + j) * lo * (L / (16 * P)));  // W_{16P}^{row lo}
 #pragma unroll
         for (int t = 0; t < 4; ++t) w[t][j] = v;
@@ -1055,11 +1282,20 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       f4 yr, yi;
-      dft_tile<SPLIT>(xh[t], xl[t], f, yr, yi);
+      if constexpr (FOLD) {
+        const h8 bh = __builtin_bit_cast(h8, xh[t]);
+        const f4 z0 = {0.f, 0.f, 0.f, 0.f};
+        yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(far, bh, z0, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(fai, bh, z0, 0, 0, 0);
+      } else {
+        dft_tile<SPLIT>(xh[t], xl[t], f, yr, yi);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float2 z = make_float2(yr[j], yi[j]);
-        if constexpr (P > 1 || XTW) z = cmul(z, w[t][j]);
+        // the stage's own twiddle (P > 1, unless folded) or the inter-pass
+        // twiddle of the last stage (P == 1)
+        if constexpr ((P > 1 && !FOLD) || (P == 1 && XTW)) z = cmul(z, w[t][j]);
         uint32_t eh = 0, el = 0;
         emit<SPLIT>(z.x, z.y, eh, el);
         oh[t][j] = eh;
@@ -1226,6 +1462,72 @@ __device__ __forceinline__ void col_stage_fused(const KParams& kp, uint32_t* lds
   }
 }
 
+// Column-pass form of row_stage_fused_mx: the 4 tiles of a lane are 4
+// adjacent columns at one low index lo, so the twiddle W_L^{(k + R0 k1) lo} is
+// one lookup per output row.
+template <class G>
+struct ColFusedMx {
+  static constexpr bool value = ColFused<G>::value && (G::R0 == 2 || G::R0 == 4);
+};
+
+template <class G, int K = 0>
+__device__ __forceinline__ void col_fused_mx_k(const KParams& kp, uint32_t* lds,
+                                               const u4 (&hh)[G::R0][4], int c, int lo) {
+  constexpr int R0 = G::R0, C = G::C;
+  constexpr int P = ColFused<G>::P, P0 = 16 * P;
+  const int g = (threadIdx.x & 63) >> 4;
+  const int k = kp.sgn < 0.f ? K : (R0 - K) % R0;  // the output this block is
+  const FOpsMx fm = load_fops_mx(kp.fimg2, K);
+  float2 w[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] = tld(kp.tw, (k + R0 * (4 * g + j)) * lo);
+  uint32_t oh[4][4];  // [t][j]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    u4 b[R0];
+#pragma unroll
+    for (int d = 0; d < R0; ++d) b[d] = u4{hh[d][0][t], hh[d][1][t], hh[d][2][t], hh[d][3][t]};
+    f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    mfma_rsum<R0, K>(fm, b, yr, yi);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 z = cmul(make_float2(yr[j], yi[j]), w[j]);
+      oh[t][j] = pack(z.x, z.y);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = (k * P0 + (4 * g + j) * P + lo) * C + c;
+    lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
+  }
+  if constexpr (K + 1 < R0) col_fused_mx_k<G, K + 1>(kp, lds, hh, c, lo);
+}
+
+template <class G>
+__device__ __forceinline__ void col_stage_fused_mx(const KParams& kp, uint32_t* lds,
+                                                   const ColCtx& cx) {
+  constexpr int R0 = G::R0, C = G::C;
+  using F = ColFused<G>;
+  constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+  for (int it = 0; it < ITF; ++it) {
+    const int sq = (wave * ITF + it) * 16 + c16;
+    const int c = 4 * (sq % (C / 4));
+    const int lo = sq / (C / 4);  // in [0, P)
+    u4 hh[R0][4];
+#pragma unroll
+    for (int d = 0; d < R0; ++d)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t a = cx.in_base + (int64_t)(d * P0 + (4 * g + i) * P + lo) * kp.s_in + c;
+        hh[d][i] = gld4(kp.in + a);
+      }
+    col_fused_mx_k<G>(kp, lds, hh, c, lo);
+  }
+}
+
 template <class G, int E, bool SPLIT, bool XTW, bool TSTORE>
 __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds, const ColCtx& cx,
                                                 const FOps& f) {
@@ -1249,7 +1551,11 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
   else
     cx.out_base = cx.outer * kp.out_outer + (cx.i0 >> kp.q_log2) * kp.qstride + (cx.i0 & (kp.q - 1));
   const FOps f = load_fops<SPLIT>(kp.fimg);
-  if constexpr (ColFused<G>::value) {
+  if constexpr (!SPLIT && ColFusedMx<G>::value) {
+    col_stage_fused_mx<G>(kp, lds, cx);
+    __syncthreads();
+    col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+  } else if constexpr (ColFused<G>::value) {
     col_stage_fused<G, SPLIT>(kp, lds, cx, f);
     __syncthreads();
     col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
@@ -1316,7 +1622,7 @@ __device__ __forceinline__ int find_job(CInt64* prefix, int njobs, int64_t w) {
 // loop-invariant addresses live to drop to one workgroup per CU).
 // (the real-input variants carry their epilogue / prologue through the
 // persistent loop: one workgroup per CU keeps them out of scratch)
-template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0>
+template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0, int WGP = 16384>
 __global__ __launch_bounds__(NT, (SPLIT || RK != 0) ? 1 : 2) void row_kernel_multi(
     const GroupHdr* __restrict__ hdr) {
   extern __shared__ uint32_t lds[];
@@ -1328,7 +1634,7 @@ __global__ __launch_bounds__(NT, (SPLIT || RK != 0) ? 1 : 2) void row_kernel_mul
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int j = find_job(prefix, njobs, w);
     const KParams kp = load_job(jobs, j);
-    row_body<L, R0, NT, SPLIT, TT, RK>(kp, w - prefix[j], lds);
+    row_body<L, R0, NT, SPLIT, TT, RK, WGP>(kp, w - prefix[j], lds);
     __syncthreads();  // the next tile's first stage rewrites LDS
   }
 }

@@ -21,7 +21,10 @@ size_t kernel_lds_bytes(const KernelKey& k) {
 }
 
 int64_t kernel_points_per_wg(const KernelKey& k) {
-  if (k.kind == K_ROW) return k.L >= 16384 ? k.L : 16384;
+  if (k.kind == K_ROW) {
+    const int64_t wgp = k.C > 0 ? k.C : 16384;  // C: points per workgroup of a row pass
+    return k.L >= wgp ? k.L : wgp;
+  }
   if (k.kind == K_PLANE) return 16384;
   if (k.kind == K_BIG) return k.L;
   return (int64_t)k.L * k.C;

@@ -102,6 +102,9 @@ struct Choice {
   int p2row = 0;     // two-pass 1D: pass 1 stores in natural order and pass 2 is a row
                      // pass over contiguous lines with a transposed store.  2D / 3D: 1
                      // keeps separate row and column passes where a plane pass exists
+  int row_pts = 0;   // points per workgroup of plain row passes: 16384 or 8192; 0 = the
+                     // measured default (8192 for split lines <= 8192 points, which
+                     // then fit two workgroups per CU, and for FP16 1024-point lines)
 };
 
 struct PlanSpec {
@@ -140,7 +143,15 @@ tcfft_status col_choice(int L, int64_t inner, int cmax, bool split, bool xtw, bo
   return TCFFT_ERR_UNSUPPORTED;
 }
 
-tcfft_status row_choice(int L, int nt, bool split, KernelKey* out) {
+tcfft_status row_choice(int L, int nt, bool split, KernelKey* out, int pts = 0) {
+  if (pts == 0) pts = ((split && L <= 8192) || (!split && L == 1024)) && nt == 256 ? 8192 : 16384;
+  if (pts == 8192 && L < 16384) {  // the smaller-workgroup variant (256 threads)
+    KernelKey k{K_ROW, L, r0_of(L), pts, 256, split ? 1 : 0, 0, 0};
+    if (find_kernel(k) && kernel_lds_bytes(k) <= kMaxLds) {
+      *out = k;
+      return TCFFT_OK;
+    }
+  }
   for (int NT : {nt, 256}) {
     KernelKey k{K_ROW, L, r0_of(L), 0, NT, split ? 1 : 0, 0, 0};
     if (find_kernel(k) && kernel_lds_bytes(k) <= kMaxLds) {
@@ -155,11 +166,13 @@ tcfft_status row_choice(int L, int nt, bool split, KernelKey* out) {
 // of lines in groups of q (line l of group b, output k at b q L + k q + l).
 tcfft_status add_row_pass(PlanSpec& ps, int L, int64_t lines, int src, int dst, int64_t q = 0) {
   PassSpec p;
-  tcfft_status st = row_choice(L, ps.ch.row_nt, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key);
+  tcfft_status st = row_choice(L, ps.ch.row_nt, ps.d.prec == TCFFT_PREC_SPLIT_FP16, &p.key,
+                               q > 0 ? 16384 : ps.ch.row_pts);
   if (st) return st;
   if (q > 0) {
     p.key.tstore = 1;
     p.key.NT = 256;
+    p.key.C = 0;
     if (!find_kernel(p.key) || q % 4 != 0 || !is_pow2(q)) return TCFFT_ERR_UNSUPPORTED;
     p.q = q;
     p.s_out = q;
@@ -323,7 +336,9 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
     // N reals = M complex words: the M-point complex plan, then (forward) or
     // before it (inverse) one elementwise pass between it and the spectrum
     PlanSpec ps;
-    if ((st = build_spec(complex_desc(d), ch, &ps))) return st;
+    Choice cc = ch;
+    cc.row_pts = 16384;  // the real-input row kernels hold 16384 points per workgroup
+    if ((st = build_spec(complex_desc(d), cc, &ps))) return st;
     const int64_t M = d.nx / 2;
     const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
     const size_t zb = (size_t)(M * d.batch) * elt, xb = (size_t)((M + 1) * d.batch) * elt;
@@ -497,7 +512,8 @@ std::string describe(const PlanSpec& ps) {
                 "{\"rank\":%d,\"dims\":[%lld%s%s%s%s],\"batch\":%lld,\"dir\":%d,\"precision\":\"%s\","
                 "\"scale_log2\":%d,\"buffer_bytes\":%zu,\"input_bytes\":%zu,\"output_bytes\":%zu,"
                 "\"workspace_bytes\":%zu,\"real\":%lld,\"real_kernel\":\"%s\","
-                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d},\"tuned\":%s,"
+                "\"choice\":{\"row_nt\":%d,\"cmax\":%d,\"factors\":[%d,%d,%d],\"chunk\":%d,\"p2row\":%d,"
+                "\"row_pts\":%d},\"tuned\":%s,"
                 "\"tuned_us\":%.2f,\"nshards\":%d,\"shard\":%d,\"shard_n1\":%lld,\"points\":%lld,"
                 "\"passes\":[",
                 ps.d.rank, (long long)ps.d.nx, ps.d.rank >= 2 ? "," : "",
@@ -508,7 +524,8 @@ std::string describe(const PlanSpec& ps) {
                 ps.real_n == 0 ? "" : ps.real_fused ? "fused" : (ps.d.dir == TCFFT_FORWARD ? "r2c_post" : "c2r_pre"),
                 ps.ch.row_nt, ps.ch.cmax,
                 ps.ch.nf > 0 ? ps.ch.f[0] : 0, ps.ch.nf > 1 ? ps.ch.f[1] : 0,
-                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.tuned ? "true" : "false",
+                ps.ch.nf > 2 ? ps.ch.f[2] : 0, ps.ch.chunk, ps.ch.p2row, ps.ch.row_pts,
+                ps.tuned ? "true" : "false",
                 ps.tuned_us, ps.d.nshards, ps.d.shard, (long long)ps.shard_n1, (long long)ps.npts);
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
@@ -571,6 +588,7 @@ struct DevPass {
   float2* xtw_lo = nullptr;  // two-level W_M tables
   float2* xtw_hi = nullptr;
   void* fimg2 = nullptr;     // A_k images of the matrix-core radix-R0 block (R0 = 2, 4)
+  void* fimg3 = nullptr;     // A_lo images of a row pass's stride-16 stage (twiddle folded in)
   int xbits = 0;
   int persist_grid = 0;      // resident workgroups for the grouped (persistent) launch
   int single_grid = 0;       // resident workgroups of the single kernel (persistent variants)
@@ -701,6 +719,10 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
         // both stages' scales: 2^-1 (radix 2 or 4) and 2^-2 (radix 16)
         launch_gen_fimg_r(dpp.fimg2, r0, sgn, noscale ? 1.0 : 0.125, s);
       }
+      if (sp.key.kind != K_BIG) {  // read by FP16 stride-16 stages that fold their twiddle
+        if ((st = dev_alloc(p, (size_t)16 * 256 * 16, &dpp.fimg3))) break;
+        launch_gen_fimg_tw(dpp.fimg3, 16, sgn, noscale ? 1.0 : 0.25, s);
+      }
       if ((st = dev_alloc(p, (size_t)sp.key.L * sizeof(float2), &t))) break;
       dpp.tw = (float2*)t;
       launch_gen_twiddles(dpp.tw, sp.key.L, sp.key.L, 1, sgn, s);
@@ -776,6 +798,7 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   kp.tw = dpp.tw;
   kp.fimg = p->fimg;
   kp.fimg2 = dpp.fimg2;
+  kp.fimg3 = dpp.fimg3;
   kp.r0scale = (float)std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L)));
   kp.r0scale2 = 1.0f;
   if (sp.key.kind == K_PLANE) {  // rows of nz, then columns of ny, each with its own radix-R0 scale
@@ -1232,14 +1255,17 @@ std::vector<Choice> candidates_base(const Desc& d) {
       if (sep && (d.rank == 1 || (plane_pts != 16384 && plane_pts != 8192 && plane_pts != 4096)))
         continue;
       for (int nt : {256, 512})
-        for (int cmax : {64, 32, 16, 8}) {
-          if (d.rank == 1 && cmax != 64) continue;
-          Choice c;
-          c.row_nt = nt;
-          c.cmax = cmax;
-          c.p2row = sep;
-          out.push_back(c);
-        }
+        for (int cmax : {64, 32, 16, 8})
+          for (int pts : {16384, 8192}) {
+            if (d.rank == 1 && cmax != 64) continue;
+            if (pts == 8192 && nt != 256) continue;  // 8192-point row workgroups run 256 threads
+            Choice c;
+            c.row_nt = nt;
+            c.cmax = cmax;
+            c.p2row = sep;
+            c.row_pts = pts;
+            out.push_back(c);
+          }
     }
     return out;
   }
@@ -1683,11 +1709,11 @@ tcfft_status tcfft_tune_cache_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return TCFFT_ERR_INVALID_ARG;
-  std::fprintf(f, "tcfft-tune 3\n");
+  std::fprintf(f, "tcfft-tune 4\n");
   for (const auto& kv : g_tune) {
     const Choice& c = kv.second.first;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax, c.nf,
-                 c.f[0], c.f[1], c.f[2], c.chunk, c.p2row, kv.second.second);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.3f\n", kv.first.c_str(), c.row_nt, c.cmax,
+                 c.nf, c.f[0], c.f[1], c.f[2], c.chunk, c.p2row, c.row_pts, kv.second.second);
   }
   std::fclose(f);
   return TCFFT_OK;
@@ -1699,16 +1725,24 @@ tcfft_status tcfft_tune_cache_load(const char* path) {
   if (!f) return TCFFT_ERR_INVALID_ARG;
   char key[160];
   int ver = 0;
-  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || ver != 3) {
+  if (std::fscanf(f, "tcfft-tune %d\n", &ver) != 1 || (ver != 3 && ver != 4)) {
     std::fclose(f);
     return TCFFT_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  Choice c;
-  double us = 0;
-  while (std::fscanf(f, "%159s %d %d %d %d %d %d %d %d %lf\n", key, &c.row_nt, &c.cmax, &c.nf,
-                     &c.f[0], &c.f[1], &c.f[2], &c.chunk, &c.p2row, &us) == 10) {
-    if (c.nf < 0 || c.nf > 3) continue;
+  while (true) {
+    // format 3 has no row_pts field
+    Choice c;
+    double us = 0;
+    const int n = ver == 4 ? std::fscanf(f, "%159s %d %d %d %d %d %d %d %d %d %lf\n", key, &c.row_nt,
+                                         &c.cmax, &c.nf, &c.f[0], &c.f[1], &c.f[2], &c.chunk,
+                                         &c.p2row, &c.row_pts, &us)
+                           : std::fscanf(f, "%159s %d %d %d %d %d %d %d %d %lf\n", key, &c.row_nt,
+                                         &c.cmax, &c.nf, &c.f[0], &c.f[1], &c.f[2], &c.chunk,
+                                         &c.p2row, &us);
+    if (n != (ver == 4 ? 11 : 10)) break;
+    if (c.nf < 0 || c.nf > 3 || (c.row_pts != 0 && c.row_pts != 8192 && c.row_pts != 16384))
+      continue;
     g_tune[key] = {c, us};
   }
   std::fclose(f);
