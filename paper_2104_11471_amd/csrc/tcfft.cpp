@@ -1358,10 +1358,12 @@ tcfft_status choose(const Desc& d, Choice* ch, bool* tuned, double* tuned_us) {
   if (!(d.flags & TCFFT_FLAG_TUNE)) return TCFFT_OK;
   std::vector<Choice> cands = candidates(d);
   if (cands.size() <= 1) return TCFFT_OK;
-  // tune on at most 2^26 points per buffer (same kernels, fewer workgroups)
+  // tune on at most 2^27 points per buffer: the batch the plan will run, up
+  // to 512 MiB of FP16 data (at half that batch the tuner's ranking of
+  // multi-pass and chunked plans did not carry over)
   Desc dt = d;
   const int64_t npts = d.nx * d.ny * d.nz;
-  dt.batch = std::max<int64_t>(1, std::min<int64_t>(d.batch, ((int64_t)1 << 26) / npts));
+  dt.batch = std::max<int64_t>(1, std::min<int64_t>(d.batch, ((int64_t)1 << 27) / npts));
   size_t bytes = 0;
   std::vector<PlanSpec> specs;
   std::vector<std::string> seen;  // candidates that build the same kernels are timed once
