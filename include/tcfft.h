@@ -134,16 +134,30 @@ tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream
 
 /*
  * Mixed-size batch execution: job j runs plans[j] on (in[j], out[j]), all jobs
- * enqueued on one stream.  Jobs of any sizes and precisions mix.  Pass l of
- * every job runs after pass l-1 of every job; within a pass level, one
- * persistent launch per kernel variant serves every job of that variant (a
- * device-resident descriptor table lists the jobs and their workgroup
- * ranges), so a batch of hundreds of uneven transforms costs a handful of
- * launches.  Each job's result is bitwise equal to tcfft_exec of that job
- * alone.  Jobs must not share an output buffer.  A plan that holds a
- * workspace (multi-pass plans; real plans whose spectrum step is a separate
- * pass) may appear in only one job of a call, since its jobs would write the
- * same intermediate; single-pass plans may repeat.
+ * enqueued on one stream.  Jobs of any sizes and precisions mix.  Each job's
+ * result is bitwise equal to tcfft_exec of that job alone.  Jobs are
+ * independent: no job may write a buffer another job of the call reads or
+ * writes (shared read-only inputs are fine).  A plan that holds a workspace
+ * (multi-pass plans; real plans whose spectrum step is a separate pass) may
+ * appear in only one job of a call, since its jobs would write the same
+ * intermediate; single-pass plans may repeat.
+ *
+ * Launch structure (Sec. 3.1, Fig. 1: the plan fixes each transform's passes
+ * once).  When every pass of every job is one of the variants compiled into
+ * the single-launch kernel (the default FP16 and split plans of 1D N <= 2^22
+ * and 2D arrays up to 2048 x 2048, 256-thread variants), the batch is ONE
+ * launch per precision class: its (job, pass) segments form a work queue
+ * ordered by (pass level, job), workgroups take tiles from an atomic counter,
+ * and a tile of pass l of a job first waits until every tile of pass l-1 of
+ * that job has finished (a wait bounded by the wall clock, 1 s by default or
+ * TCFFT_FUSED_WAIT_US microseconds from the environment; a wait that runs out
+ * fails the whole launch, which then drains, and is counted by
+ * tcfft_fused_wait_failures).  Otherwise (other variants, real plans with a
+ * fused spectrum step, the single-pass 65536 kernel) pass l of every job runs
+ * after pass l-1 of every job, one persistent launch per (level, variant)
+ * reading a device-resident descriptor table.  TCFFT_FUSED=0 in the
+ * environment selects the second form for every batch.  Chunked FP16 plans
+ * run on their own after the batch.
  * Errors: as tcfft_exec; INVALID_ARG for njobs < 0, null arrays or a
  * workspace-holding plan listed twice; ALLOC when the descriptor table cannot
  * be allocated (stream-ordered).
@@ -369,6 +383,14 @@ int64_t tcfft_server_now_ns(void);
 
 /* Static text for a status code. */
 const char* tcfft_status_string(tcfft_status s);
+
+/*
+ * Diagnostics of the single-launch batch path (tcfft_exec_many): the number of
+ * dependency waits, on the current device since the library was loaded, that
+ * ran past their bound and failed their launch.  Synchronous (a device copy);
+ * *count is untouched on error.  Errors: INVALID_ARG (null), NO_DEVICE.
+ */
+tcfft_status tcfft_fused_wait_failures(unsigned* count);
 
 /* Library version string. */
 const char* tcfft_version(void);

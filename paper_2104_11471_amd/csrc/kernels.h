@@ -78,6 +78,42 @@ struct GroupHdr {
   int64_t reserved;
 };
 
+// Single-launch mixed batch (k_fused.hip).  The batch's passes form a queue of
+// segments, one per (job, pass), in the order (pass level, job); segment s
+// owns queue indices [start, start + tiles) and runs fused variant `var` with
+// descriptor kps[kp]; it may start a tile only once segment `dep` (the same
+// job's previous pass, or -1) has finished all its tiles.
+struct FusedSeg {
+  int64_t start;
+  int64_t tiles;
+  int32_t var;
+  int32_t dep;
+  int32_t kp;
+  int32_t pad;
+};
+static_assert(sizeof(FusedSeg) == 32, "FusedSeg layout");
+
+// Header of one fused launch, in device memory.  ctr[0] is the queue head,
+// ctr[1] the wait-failure flag, ctr[2 + s] the finished tiles of segment s; the
+// host uploads them as zeros with the tables.  lds_slot: LDS word index (past
+// the largest variant's LDS) used to broadcast the dequeued tile.
+struct FusedHdr {
+  const KParams* kps;
+  const FusedSeg* segs;
+  int* ctr;
+  int64_t nsegs;
+  int64_t total;
+  int64_t lds_slot;
+  int64_t wait_ticks;  // bound of one dependency wait, wall-clock counter ticks
+};
+
+// Fused variant id of `key` in the single-launch kernel, or -1.
+int fused_variant(const KernelKey& key);
+// The single-launch kernel of one precision class (FP16 or split).
+const void* fused_kernel(bool split);
+// Device-wide count of dependency waits that gave up (read with a copy).
+hipError_t fused_wait_failures(unsigned* count);
+
 typedef void (*KernelFn)(KParams);
 typedef void (*MultiFn)(const GroupHdr*);
 

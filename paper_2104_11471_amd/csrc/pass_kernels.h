@@ -62,7 +62,7 @@ __device__ __forceinline__ void gst4(uint32_t* ptr, u4 v) { *(TCFFT_GLOBAL u4*)(
 // Row passes stream their lines through once with non-temporal accesses
 // (measured faster for contiguous 16-byte-per-lane lines; column passes, whose
 // rows are 64-256-byte runs, keep the default cache policy, which measured
-// faster for them).
+// faster for them, and so do the loads of a plane pass's row half).
 __device__ __forceinline__ u4 rld4(const uint32_t* ptr) {
   return __builtin_nontemporal_load((const TCFFT_GLOBAL u4*)(ptr));
 }
@@ -149,9 +149,10 @@ __device__ __forceinline__ float2 value(uint32_t h, uint32_t l) {
 // ===========================================================================
 // Row kernel: TPB contiguous lines per workgroup, LDS position p = tau*L + j.
 // ===========================================================================
-template <int L_, int R0_, int NT_, int WGP_ = 16384>
+template <int L_, int R0_, int NT_, int WGP_ = 16384, bool NTL_ = true>
 struct RowGeom {
   static constexpr int L = L_, R0 = R0_, NT = NT_;
+  static constexpr bool NTL = NTL_;  // HBM loads non-temporal
   static constexpr int S = (ilog2c(L) - ilog2c(R0)) / 4;
   static_assert(pow16(S) * R0 == L, "L must be R0 * 16^S");
   // points per workgroup: 16384 = 4 quads per wave at 256 threads (64 KB of
@@ -168,6 +169,13 @@ struct RowGeom {
   static constexpr int P0 = L / R0;
   static constexpr int NCQ0 = PTS / R0 / 4;
 };
+
+// HBM load of a row pass (cache policy of the geometry).
+template <class G>
+__device__ __forceinline__ u4 row_ld4(const uint32_t* ptr) {
+  if constexpr (G::NTL) return rld4(ptr);
+  else return gld4(ptr);
+}
 
 // Position of element (row, col) of a radix-16 stage with digit stride P > 1.
 template <int L, int P>
@@ -228,8 +236,8 @@ __device__ __forceinline__ void row_stage_r0(const KParams& kp, uint32_t* lds, i
         if constexpr (SPLIT) ll[d] = lds_ld4(ldsl, p);
         else ll[d] = u4{0, 0, 0, 0};
       } else {
-        hh[d] = rld4(kp.in + g0 + p);
-        if constexpr (SPLIT) ll[d] = rld4(kp.in + kp.in_plane + g0 + p);
+        hh[d] = row_ld4<G>(kp.in + g0 + p);
+        if constexpr (SPLIT) ll[d] = row_ld4<G>(kp.in + kp.in_plane + g0 + p);
         else ll[d] = u4{0, 0, 0, 0};
       }
     }
@@ -296,8 +304,8 @@ __device__ __forceinline__ void row_stage16_load(const KParams& kp, int valid, i
     for (int i = 0; i < 4; ++i) {
       int p = row_pos_t<L, P>(col0, 4 * g + i);
       if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
-      r.h[qq][i] = rld4(kp.in + g0 + p);
-      if constexpr (SPLIT) r.l[qq][i] = rld4(kp.in + kp.in_plane + g0 + p);
+      r.h[qq][i] = row_ld4<G>(kp.in + g0 + p);
+      if constexpr (SPLIT) r.l[qq][i] = row_ld4<G>(kp.in + kp.in_plane + g0 + p);
       else r.l[qq][i] = u4{0, 0, 0, 0};
     }
   }
@@ -346,8 +354,8 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
           rl[i] = pre->l[qq][i];
         } else if constexpr (SRCG) {
           if (G::TPB > 1 && p / L >= valid) p -= (p / L) * L;  // clamp to line 0
-          rh[i] = rld4(kp.in + g0 + p);
-          if constexpr (SPLIT) rl[i] = rld4(kp.in + kp.in_plane + g0 + p);
+          rh[i] = row_ld4<G>(kp.in + g0 + p);
+          if constexpr (SPLIT) rl[i] = row_ld4<G>(kp.in + kp.in_plane + g0 + p);
         } else {
           rh[i] = lds_ld4(lds, p);
           if constexpr (SPLIT) rl[i] = lds_ld4(ldsl, p);
@@ -371,8 +379,8 @@ __device__ __forceinline__ void row_stage16(const KParams& kp, uint32_t* lds, in
         if constexpr (SRCG && G::TPB > 1) tau = tau < valid ? tau : 0;
         const int p = tau * L + posrev_hi<R0, S>(TT ? klowT : col % (L / 16)) * 16 + 4 * g;
         if constexpr (SRCG) {
-          xh[t] = rld4(kp.in + g0 + p);
-          if constexpr (SPLIT) xl[t] = rld4(kp.in + kp.in_plane + g0 + p);
+          xh[t] = row_ld4<G>(kp.in + g0 + p);
+          if constexpr (SPLIT) xl[t] = row_ld4<G>(kp.in + kp.in_plane + g0 + p);
         } else {
           xh[t] = lds_ld4(lds, p);
           if constexpr (SPLIT) xl[t] = lds_ld4(ldsl, p);
@@ -553,8 +561,8 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
           if constexpr (SPLIT) ll[d][i] = lds_ld4(ldsl, p);
           else ll[d][i] = u4{0, 0, 0, 0};
         } else {
-          hh[d][i] = rld4(kp.in + g0 + p);
-          if constexpr (SPLIT) ll[d][i] = rld4(kp.in + kp.in_plane + g0 + p);
+          hh[d][i] = row_ld4<G>(kp.in + g0 + p);
+          if constexpr (SPLIT) ll[d][i] = row_ld4<G>(kp.in + kp.in_plane + g0 + p);
           else ll[d][i] = u4{0, 0, 0, 0};
         }
       }
@@ -734,9 +742,16 @@ __device__ __forceinline__ void row_fused_mx_k(const KParams& kp, uint32_t* lds,
   if constexpr (K + 1 < R0) row_fused_mx_k<G, K + 1>(kp, lds, hh, tau, lo0);
 }
 
+// Inputs of the fused matrix-core block: per iteration, rows 4g..4g+3 of every
+// radix-R0 digit d at 4 consecutive low indices lo0..lo0+3.
+template <class G>
+struct RowMxRegs {
+  u4 hh[RowFused<G>::ITF][G::R0][4];  // [it][d][row i]
+};
+
 template <class G, bool SRCL = false>
-__device__ __forceinline__ void row_stage_fused_mx(const KParams& kp, uint32_t* lds, int valid,
-                                                   int64_t g0) {
+__device__ __forceinline__ void row_fused_mx_load(const KParams& kp, const uint32_t* lds,
+                                                  int valid, int64_t g0, RowMxRegs<G>& r) {
   constexpr int L = G::L, R0 = G::R0;
   using F = RowFused<G>;
   constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
@@ -748,17 +763,37 @@ __device__ __forceinline__ void row_stage_fused_mx(const KParams& kp, uint32_t* 
     const int tau = sq / (P / 4);
     const int lo0 = 4 * (sq % (P / 4));
     const int taul = (!SRCL && G::TPB > 1 && tau >= valid) ? 0 : tau;
-    u4 hh[R0][4];  // [d][row i]: 4 consecutive low indices lo0..lo0+3
 #pragma unroll
     for (int d = 0; d < R0; ++d)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int p = taul * L + d * P0 + (4 * g + i) * P + lo0;
-        if constexpr (SRCL) hh[d][i] = lds_ld4(lds, p);
-        else hh[d][i] = rld4(kp.in + g0 + p);
+        if constexpr (SRCL) r.hh[it][d][i] = lds_ld4(lds, p);
+        else r.hh[it][d][i] = row_ld4<G>(kp.in + g0 + p);
       }
-    row_fused_mx_k<G>(kp, lds, hh, tau, lo0);
   }
+}
+
+template <class G>
+__device__ __forceinline__ void row_fused_mx_compute(const KParams& kp, uint32_t* lds,
+                                                     const RowMxRegs<G>& r) {
+  using F = RowFused<G>;
+  constexpr int P = F::P, ITF = F::ITF;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c16 = lane & 15;
+#pragma unroll
+  for (int it = 0; it < ITF; ++it) {
+    const int sq = (wave * ITF + it) * 16 + c16;
+    row_fused_mx_k<G>(kp, lds, r.hh[it], sq / (P / 4), 4 * (sq % (P / 4)));
+  }
+}
+
+template <class G, bool SRCL = false>
+__device__ __forceinline__ void row_stage_fused_mx(const KParams& kp, uint32_t* lds, int valid,
+                                                   int64_t g0) {
+  RowMxRegs<G> r;
+  row_fused_mx_load<G, SRCL>(kp, lds, valid, g0, r);
+  row_fused_mx_compute<G>(kp, lds, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,7 +1044,8 @@ __device__ __forceinline__ void real_pre(const KParams& kp, uint32_t* lds, int v
 // 3 results stay in LDS in natural order (the first half of a plane pass).
 template <int L, int R0, int NT, bool SPLIT, bool TT = false, int RK = 0, int WGP = 16384>
 __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t* lds) {
-  using G = RowGeom<L, R0, NT, WGP>;
+  // a plane pass's row half (RK == 3) loads with the default cache policy
+  using G = RowGeom<L, R0, NT, WGP, RK != 3>;
   static_assert(RK == 0 || (!TT && G::S >= 1 && L >= 64), "real / plane variants");
   constexpr bool KEEP = RK == 1 || RK == 3, SRCL = RK == 2;
   const int64_t t0 = wg * G::TPB;
@@ -1047,17 +1083,17 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
   }
 }
 
-// Whether a row pass runs as a pipelined persistent kernel: split data (two LDS
-// planes, so one workgroup per CU) whose first stage is radix-16 from HBM with
-// P > 1, followed by at least one LDS stage.  With nothing else resident, the
-// workgroup overlaps its own next loads with its LDS stages.  FP16 passes keep
-// two workgroups per CU that overlap each other at least as well; passes with
-// a fused radix-2/4 first stage measured slower with the prefetch (or ran out
-// of registers).
+// Whether a row pass runs as a pipelined persistent kernel: passes whose first
+// stage is radix-16 from HBM with P > 1, followed by at least one LDS stage,
+// at 256 threads.  Workgroup b runs tiles b, b + grid, ... and overlaps its own
+// next loads with its LDS stages: split data (two LDS planes, one workgroup
+// per CU) and FP16 (4096: 221 -> 202 us for 2^27 points).  Passes with a fused
+// radix-2/4 first stage keep one tile per workgroup: holding the next tile's
+// inputs over the LDS stages leaves them one workgroup per CU (16384: 244 ->
+// 259 us).
 template <class G, bool SPLIT>
 struct RowPipe {
-  static constexpr bool value =
-      SPLIT && G::NT == 256 && !RowFused<G>::value && G::R0 == 1 && G::S >= 2;
+  static constexpr bool value = G::NT == 256 && !RowFused<G>::value && G::R0 == 1 && G::S >= 2;
 };
 
 // Pipelined persistent row pass: workgroup b runs tiles b, b + grid, ...; the

@@ -552,7 +552,7 @@ std::string describe(const PlanSpec& ps) {
                   "\"s_in\":%lld,\"s_out\":%lld,\"xmod\":%lld,\"real\":%d,\"blocks\":%lld,"
                   "\"in_outer\":%lld,\"out_outer\":%lld,\"q\":%lld,\"qstride\":%lld,"
                   "\"xdiv\":%lld,\"xoff\":%lld,\"tblk\":%lld,\"tblk_stride\":%lld,\"lines\":%lld,"
-                  "\"tpb\":%lld}",
+                  "\"tpb\":%lld,\"fused\":%d}",
                   i ? "," : "",
                   p.key.kind == K_ROW ? "row"
                   : p.key.kind == K_BIG ? "big"
@@ -563,7 +563,7 @@ std::string describe(const PlanSpec& ps) {
                   (long long)p.blocks, (long long)p.in_outer, (long long)p.out_outer, (long long)p.q,
                   (long long)p.qstride, (long long)p.xdiv, (long long)p.xoff,
                   (long long)(p.tblk > 0 ? p.tblk : p.key.L), (long long)p.tblk_stride,
-                  (long long)p.ntrans, (long long)p.tpb);
+                  (long long)p.ntrans, (long long)p.tpb, fused_variant(p.key) >= 0 ? 1 : 0);
     s += b;
   }
   s += "]}";
@@ -1008,6 +1008,69 @@ struct Group {
   std::vector<int64_t> prefix{0};
 };
 
+// ---------------------------------------------------------------------------
+// Single-launch path (k_fused.hip): when every pass of every job has a fused
+// variant, the whole batch is one persistent launch per precision class, its
+// (job, pass) segments queued in the order (pass level, job), a job's pass
+// waiting on that job's previous pass only.  TCFFT_FUSED=0 in the environment
+// selects the per-(level, variant) launches instead; TCFFT_FUSED_WAIT_US
+// bounds one dependency wait (default 1 s).
+bool fused_on() {
+  const char* e = std::getenv("TCFFT_FUSED");
+  return !(e && e[0] == '0');
+}
+
+int64_t fused_wait_us() {
+  const char* e = std::getenv("TCFFT_FUSED_WAIT_US");
+  if (!e || !*e) return 1000000;
+  const long long v = std::atoll(e);
+  return v < 0 ? 0 : (int64_t)v;
+}
+
+constexpr size_t kFusedLdsMax = 163840;  // LDS of one CU
+
+struct FusedDev {
+  bool ready = false;
+  int64_t clock_khz = 0;
+};
+std::mutex g_fused_mu;
+std::map<int, FusedDev> g_fused_dev;
+
+// One-time set-up of the fused kernels on the current device (their LDS
+// limit); returns the device's wall-clock rate.
+tcfft_status fused_prepare(int64_t* clock_khz) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TCFFT_ERR_NO_DEVICE;
+  std::lock_guard<std::mutex> lk(g_fused_mu);
+  FusedDev& fd = g_fused_dev[dev];
+  if (!fd.ready) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        khz <= 0) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_NO_DEVICE;
+    }
+    for (bool sp : {false, true})
+      if (hipFuncSetAttribute(fused_kernel(sp), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kFusedLdsMax) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
+    fd.clock_khz = khz;
+    fd.ready = true;
+  }
+  *clock_khz = fd.clock_khz;
+  return TCFFT_OK;
+}
+
+struct FusedClass {
+  std::vector<KParams> kps;
+  std::vector<FusedSeg> segs;
+  size_t lds = 0;
+  int64_t total = 0;
+  size_t off = 0;  // byte offset of the class's header in the upload
+};
+
 }  // namespace
 
 size_t tcfft_internal_desc_bytes(int max_jobs) {
@@ -1017,6 +1080,149 @@ size_t tcfft_internal_desc_bytes(int max_jobs) {
 
 tcfft::GraphCache::~GraphCache() {
   for (auto& kv : execs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+}
+
+// The batch as one fused launch per precision class.  *applied is false (and
+// nothing is enqueued) when some pass has no fused variant or the batch does
+// not fit the fused kernel's limits; the caller then uses grouped launches.
+static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hipStream_t s,
+                               void* desc_arena, size_t arena_cap, tcfft::GraphCache* graphs,
+                               bool arg_upload, bool* applied) {
+  *applied = false;
+  FusedClass cls[2];
+  std::vector<int> last(njobs, -1);  // the job's latest segment
+  std::string sig = "fused";
+  for (int lv = 0; lv < levels; ++lv)
+    for (int j = 0; j < njobs; ++j) {
+      tcfft_plan_s* p = jobs[j].plan;
+      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || lv >= (int)p->dp.size()) continue;
+      const DevPass& dpp = p->dp[lv];
+      const int var = fused_variant(dpp.spec.key);
+      if (var < 0) return TCFFT_OK;
+      FusedClass& c = cls[dpp.spec.key.split ? 1 : 0];
+      int64_t tiles = 0;
+      c.kps.push_back(make_kparams(p, dpp, jobs[j].in, jobs[j].out, jobs[j].batch, jobs[j].ws, &tiles));
+      FusedSeg sg{};
+      sg.start = c.total;
+      sg.tiles = tiles;
+      sg.var = var;
+      sg.dep = last[j];
+      sg.kp = (int32_t)c.kps.size() - 1;
+      last[j] = (int)c.segs.size();
+      c.segs.push_back(sg);
+      c.total += tiles;
+      c.lds = std::max(c.lds, dpp.spec.lds);
+      sig.append((const char*)&var, sizeof var);
+    }
+  // tables: per class the header, descriptors, segments and counters (8-byte aligned)
+  size_t bytes = 0;
+  int64_t clock_khz = 0;
+  for (int k = 0; k < 2; ++k) {
+    FusedClass& c = cls[k];
+    if (c.segs.empty()) continue;
+    c.lds = (c.lds + 15) / 16 * 16;
+    if (c.lds + 16 > kFusedLdsMax || c.total >= ((int64_t)1 << 30)) return TCFFT_OK;
+    tcfft_status st = fused_prepare(&clock_khz);
+    if (st) return st;
+    c.off = bytes;
+    bytes += sizeof(FusedHdr) + c.kps.size() * sizeof(KParams) + c.segs.size() * sizeof(FusedSeg) +
+             ((2 + c.segs.size()) * sizeof(int) + 7) / 8 * 8;
+  }
+  if (bytes == 0) return TCFFT_OK;
+  uint8_t* dmem = (uint8_t*)desc_arena;
+  if (dmem && bytes > arena_cap) return TCFFT_ERR_ALLOC;
+  *applied = true;
+  if (!dmem) {
+    void* m = nullptr;
+    if (hipMallocAsync(&m, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_ALLOC;
+    }
+    dmem = (uint8_t*)m;
+  }
+  std::vector<uint8_t> host(bytes, 0);  // counters upload as zeros
+  const int64_t ticks = fused_wait_us() * clock_khz / 1000;
+  for (int k = 0; k < 2; ++k) {
+    const FusedClass& c = cls[k];
+    if (c.segs.empty()) continue;
+    const size_t kb = c.kps.size() * sizeof(KParams), sb = c.segs.size() * sizeof(FusedSeg);
+    FusedHdr h{};
+    h.kps = (const KParams*)(dmem + c.off + sizeof(FusedHdr));
+    h.segs = (const FusedSeg*)(dmem + c.off + sizeof(FusedHdr) + kb);
+    h.ctr = (int*)(dmem + c.off + sizeof(FusedHdr) + kb + sb);
+    h.nsegs = (int64_t)c.segs.size();
+    h.total = c.total;
+    h.lds_slot = (int64_t)(c.lds / 4);
+    h.wait_ticks = ticks;
+    std::memcpy(host.data() + c.off, &h, sizeof h);
+    std::memcpy(host.data() + c.off + sizeof(FusedHdr), c.kps.data(), kb);
+    std::memcpy(host.data() + c.off + sizeof(FusedHdr) + kb, c.segs.data(), sb);
+  }
+  tcfft_status st = TCFFT_OK;
+  if (arg_upload) {
+    if (launch_write_words(dmem, host.data(), bytes, s) != hipSuccess) return TCFFT_ERR_LAUNCH;
+  } else if ((st = upload(dmem, host.data(), bytes, s))) {
+    return st;
+  }
+  // one workgroup per tile; a captured launch takes the next power of two
+  // (workgroups past the total exit at once), so one graph serves every batch
+  // of the same variant sequence and tile-count bucket
+  auto grid_of = [](int64_t total, bool bucket) {
+    int64_t g = std::max<int64_t>(1, total);
+    if (bucket) g = (int64_t)1 << ilog2(2 * g - 1);
+    return g;
+  };
+  auto launch_all = [&](bool bucket) -> tcfft_status {
+    for (int k = 0; k < 2; ++k) {
+      const FusedClass& c = cls[k];
+      if (c.segs.empty()) continue;
+      const FusedHdr* hdr = (const FusedHdr*)(dmem + c.off);
+      const int64_t want = grid_of(c.total, bucket);
+      void* args[] = {&hdr};
+      if (hipLaunchKernel(fused_kernel(k == 1), dim3((unsigned)std::max<int64_t>(1, want)),
+                          dim3(256), args, c.lds + 16, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
+    }
+    return TCFFT_OK;
+  };
+  bool use_graph = false;
+  if (graphs && desc_arena) {
+    for (int k = 0; k < 2; ++k) {
+      const int64_t g = cls[k].segs.empty() ? 0 : grid_of(cls[k].total, true);
+      sig.append((const char*)&g, sizeof g);
+    }
+    use_graph = graphs->execs.count(sig) > 0 || ++graphs->seen[sig] >= graphs->capture_after;
+  }
+  if (use_graph) {
+    auto it = graphs->execs.find(sig);
+    if (it == graphs->execs.end()) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCFFT_ERR_LAUNCH;
+      }
+      tcfft_status lst = launch_all(true);
+      const hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (lst || ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        return lst ? lst : TCFFT_ERR_LAUNCH;
+      }
+      (void)hipGraphDestroy(graph);
+      it = graphs->execs.emplace(sig, (void*)exec).first;
+    }
+    if (hipGraphLaunch((hipGraphExec_t)it->second, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return TCFFT_ERR_LAUNCH;
+    }
+  } else if ((st = launch_all(false))) {
+    return st;
+  }
+  if (!desc_arena) (void)hipFreeAsync(dmem, s);  // stream-ordered: after the launch
+  return hipGetLastError() == hipSuccess ? TCFFT_OK : TCFFT_ERR_LAUNCH;
 }
 
 tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStream_t s,
@@ -1031,6 +1237,12 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
       continue;
     }
     levels = std::max(levels, (int)p->dp.size());
+  }
+  if (levels > 0 && fused_on()) {
+    bool applied = false;
+    tcfft_status st = exec_fused(jobs, njobs, levels, s, desc_arena, arena_cap, graphs, arg_upload,
+                                 &applied);
+    if (st || applied) return st;
   }
   // every (pass level, variant) group of the batch, in launch order
   std::vector<Group> groups;
@@ -1615,6 +1827,22 @@ tcfft_status tcfft_exec_many(const tcfft_plan* plans, const void* const* in, voi
   } catch (...) {
     return TCFFT_ERR_INTERNAL;
   }
+}
+
+tcfft_status tcfft_fused_wait_failures(unsigned* count) {
+  if (!count) return TCFFT_ERR_INVALID_ARG;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_NO_DEVICE;
+  }
+  unsigned v = 0;
+  if (fused_wait_failures(&v) != hipSuccess) {
+    (void)hipGetLastError();
+    return TCFFT_ERR_NO_DEVICE;
+  }
+  *count = v;
+  return TCFFT_OK;
 }
 
 tcfft_status tcfft_exec_many_static(const tcfft_plan* plans, const void* const* in,

@@ -40,7 +40,7 @@ EXPORTS = ["tcfft_plan_create", "tcfft_plan_1d", "tcfft_plan_2d", "tcfft_exec", 
            "tcfft_server_submit", "tcfft_server_poll", "tcfft_server_wait_idle",
            "tcfft_server_get_stats", "tcfft_server_destroy", "tcfft_server_now_ns",
            "tcfft_plan_create_shard", "tcfft_exec_shard", "tcfft_shard_dry_run",
-           "tcfft_exec_many_static", "tcfft_server_cancel"]
+           "tcfft_exec_many_static", "tcfft_server_cancel", "tcfft_fused_wait_failures"]
 
 
 class TcfftError(RuntimeError):
@@ -72,6 +72,8 @@ def _load() -> ctypes.CDLL:
     lib.tcfft_exec_many.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
     lib.tcfft_exec_many_static.argtypes = [P(vp), P(vp), P(vp), ctypes.c_int, vp]
     lib.tcfft_exec_many_static.restype = ctypes.c_int
+    lib.tcfft_fused_wait_failures.argtypes = [P(ctypes.c_uint)]
+    lib.tcfft_fused_wait_failures.restype = ctypes.c_int
     lib.tcfft_exec_passes.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.tcfft_plan_destroy.argtypes = [vp]
     lib.tcfft_plan_scale_log2.argtypes = [vp]
@@ -342,6 +344,15 @@ def exec_many(plans, xs, outs, stream=None, static: bool = False) -> None:
     st = fn(hp, ip, op, n, VP(s.cuda_stream))
     if st != 0:
         raise TcfftError(st, "tcfft_exec_many_static" if static else "tcfft_exec_many")
+
+
+def fused_wait_failures() -> int:
+    """Dependency waits of single-launch batches that ran out (current device)."""
+    v = ctypes.c_uint(0)
+    st = lib.tcfft_fused_wait_failures(ctypes.byref(v))
+    if st != 0:
+        raise TcfftError(st, "tcfft_fused_wait_failures")
+    return v.value
 
 
 def shard_dry_run(n: int, batch: int, nshards: int, shard: int, direction: int = FORWARD,
