@@ -41,9 +41,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_launches(fn, reps: int, stream) -> float:
-    """Average duration (s) of fn() over reps, HIP events on `stream`."""
+def time_launches(fn, reps: int, stream, warm: int = 5) -> float:
+    """Average duration (s) of fn() over reps, HIP events on `stream`, after
+    `warm` untimed calls (clocks ramp back up after the GPU idled)."""
     import torch
+    for _ in range(warm):
+        fn()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
@@ -106,6 +109,8 @@ def pass_times(plan, x, y, stream, reps: int = 10) -> list:
     """HIP-event time (us) of each pass of a multi-pass plan: the first k
     passes timed alone (tcfft_exec_passes), differences of the prefixes."""
     pref = [0.0]
+    for _ in range(20):  # steady clocks (the caller may have left the GPU idle)
+        plan.run_passes(x, plan.num_launches, out=y, stream=stream)
     for k in range(1, plan.num_launches + 1):
         pref.append(time_launches(lambda: plan.run_passes(x, k, out=y, stream=stream), reps,
                                   stream) * 1e6)
@@ -237,6 +242,42 @@ def other_workloads(stream) -> dict:
             del xd, yd, p
             torch.cuda.empty_cache()
     out.update(real_workloads(stream))
+    out.update(fp64_workloads(stream))
+    return out
+
+
+def fp64_workloads(stream) -> dict:
+    """FP64 matrix-core path: batched 1D N = 4096 x 32768 and 256 x 524288
+    (2^27 points, 2 GiB of complex FP64 each way): time, algorithmic HBM
+    bytes (16 B read + 16 B written per point) and the FP64 matrix-core work
+    (16 v_mfma_f64_16x16x4f64 = 32768 flops per 256 points per radix-16
+    stage) against the 78.6 TFLOP/s FP64 peak; row-0 accuracy against the
+    oracle.  Not part of `value`."""
+    import torch
+    import oracle
+    from paper_2104_11471_amd import inputs, tcfft
+    out = {}
+    for n in (4096, 256):
+        batch = TOTAL_POINTS // n
+        z = inputs.uniform_f64((batch, n), 3)
+        xd = torch.from_numpy(np.stack([z.real, z.imag], -1)).cuda()
+        yd = torch.empty_like(xd)
+        p = tcfft.Plan((n,), batch, tcfft.FORWARD, "fp64")
+        dt = time_launches(lambda: p(xd, yd, stream=stream), 10, stream)
+        y0 = yd[0].cpu().numpy()
+        err = float(oracle.rel_l2(y0[:, 0] + 1j * y0[:, 1], oracle.fft(z[0], -1), axis=None))
+        stages = int(round(math.log2(n))) // 4
+        mfma_flop = 128.0 * stages * TOTAL_POINTS
+        key = f"1d_{n}x{batch}_fp64"
+        out[key] = {"us": round(dt * 1e6, 1),
+                    "gbs_alg": round(32.0 * TOTAL_POINTS / dt / 1e9, 1),
+                    "hbm_frac_alg": round(32.0 * TOTAL_POINTS / dt / 1e9 / HBM_PEAK_GBS, 4),
+                    "mfma_tflops": round(mfma_flop / dt / 1e12, 2),
+                    "mfma_frac": round(mfma_flop / dt / 1e12 / 78.6, 4),
+                    "rel_l2_row0": err}
+        log(f"{key}: {out[key]}")
+        del xd, yd, p, z
+        torch.cuda.empty_cache()
     return out
 
 
@@ -293,6 +334,60 @@ def real_workloads(stream) -> dict:
     return out
 
 
+def mixed_batch_leg(stream, single_pass: bool = False) -> dict:
+    """One mixed batch of 256 requests drawn from the serving population (with
+    `single_pass`, only its 1D requests of <= 16384 points), run by
+    tcfft_exec_many as single launches (k_fused.hip; TCFFT_FUSED=1) and as
+    per-(level, variant) grouped launches (TCFFT_FUSED=0): time per batch and
+    launch counts.  Not part of `value`."""
+    import torch
+    from paper_2104_11471_amd import inputs, tcfft
+    reqs = inputs.serving_stream(rate_hz=20000.0, duration_s=2.0, seed=7)
+    if single_pass:
+        reqs = [r for r in reqs if r.rank == 1 and r.dims[0] <= 16384]
+    reqs = reqs[:256]
+    plans, xs, ys = [], [], []
+    cache = {}
+    groups, classes = set(), set()
+    for r in reqs:
+        prec = "split" if r.split else "fp16"
+        key = (tuple(r.dims), r.batch, prec)
+        if key not in cache:
+            cache[key] = tcfft.Plan(r.dims, r.batch, precision=prec)
+        p = cache[key]
+        if p.workspace_bytes > 0 and any(q is p for q in plans):
+            continue  # a workspace-holding plan runs once per call
+        plans.append(p)
+        shape = (r.batch,) + tuple(r.dims)
+        host = (np.stack(inputs.to_split(inputs.uniform_f64(shape, len(xs)))) if r.split
+                else inputs.uniform(shape, len(xs)))
+        xs.append(torch.from_numpy(host).cuda())
+        ys.append(torch.empty_like(xs[-1]))
+        for lv, q in enumerate(p.describe()["passes"]):
+            groups.add((lv, q["kernel"], q["L"], q["C"], q["NT"], q["xtw"], q["tstore"], prec))
+            classes.add((lv, prec, q["lds"] > 65536))
+    out = {"jobs": len(plans), "transforms": int(sum(p.batch for p in plans))}
+    for name, env in (("fused", "1"), ("fused_dep", "2"), ("grouped", "0")):
+        old = os.environ.get("TCFFT_FUSED")
+        if env is not None:
+            os.environ["TCFFT_FUSED"] = env
+        try:
+            for _ in range(3):
+                tcfft.exec_many(plans, xs, ys, stream=stream)
+            dt = time_launches(lambda: tcfft.exec_many(plans, xs, ys, stream=stream), 50, stream)
+        finally:
+            if old is None:
+                os.environ.pop("TCFFT_FUSED", None)
+            else:
+                os.environ["TCFFT_FUSED"] = old
+        out[f"{name}_us"] = round(dt * 1e6, 1)
+    out["fused_launches"] = len(classes)  # one per (pass level, precision, LDS class)
+    out["grouped_launches"] = len(groups)
+    out["fused_wait_failures"] = tcfft.fused_wait_failures()
+    log(f"mixed batch: {out}")
+    return out
+
+
 def serving_leg(seconds: float) -> dict:
     """Poisson stream (20k req/s) of the mixed request population through the
     continuous-batching scheduler: p50/p99 latency and throughput.  Payloads
@@ -325,8 +420,18 @@ def serving_leg(seconds: float) -> dict:
 
     main = one(False, 0)
     alt = one(True, 100)
-    main["graphs_window100"] = {k: alt[k] for k in ("p50_us", "p99_us", "max_us", "req_per_s",
-                                                    "batches", "max_batch_jobs")}
+    keys = ("p50_us", "p99_us", "max_us", "req_per_s", "batches", "max_batch_jobs")
+    main["graphs_window100"] = {k: alt[k] for k in keys}
+    old = os.environ.get("TCFFT_FUSED")
+    os.environ["TCFFT_FUSED"] = "0"
+    try:
+        grouped = one(False, 0)
+    finally:
+        if old is None:
+            os.environ.pop("TCFFT_FUSED", None)
+        else:
+            os.environ["TCFFT_FUSED"] = old
+    main["grouped_launches"] = {k: grouped[k] for k in keys}
     return main
 
 
@@ -372,14 +477,14 @@ def run_workloads(specs, reps: int, stream) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated subset of the sizes (profiling)")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
-    ap.add_argument("--serve-seconds", type=float, default=1.0,
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson serving stream (0 = skip)")
     ap.add_argument("--wisdom", default="",
                     help="load this autotuner cache before planning (skips re-tuning: a profiled "
@@ -458,7 +563,11 @@ def main():
     rng = np.random.default_rng(1)
     for n in SIZES:
         batch = TOTAL_POINTS // n
-        dt = time_launches(lambda: plans[n](xd[n], yd[n], stream=stream), 10, stream)
+        # the accuracy check of the previous size leaves the GPU idle for
+        # seconds: bring the clocks back up before timing
+        for _ in range(20):
+            plans[n](xd[n], yd[n], stream=stream)
+        dt = time_launches(lambda: plans[n](xd[n], yd[n], stream=stream), 20, stream)
         emax, erms, eq5, ns = accuracy_sample(plans[n], xd[n], yd[n], xs[n][0], xs[n][1], rng)
         per[n] = {"us": round(dt * 1e6, 2), "gflops": round(flops(n, batch) / dt / 1e9, 1),
                   "gbs_alg": round(8.0 * TOTAL_POINTS / dt / 1e9, 1),
@@ -504,8 +613,10 @@ def main():
         del x32, y32, p32
 
     others = None
+    mixed = None
     if not args.no_others:
         others = other_workloads(stream)
+        mixed = mixed_batch_leg(stream)
 
     serving = None
     if args.serve_seconds > 0:
@@ -534,6 +645,7 @@ def main():
         "roofline": roofline,
         "comparator_fp32_radix2": comparator,
         "serving": serving,
+        "mixed_batch": mixed,
         "other_workloads": others,
         "cpu_baseline": cpu,
     }

@@ -26,6 +26,11 @@
  *                          hi + 2^-11 * lo.
  *   TCFFT_PREC_FP32_RADIX2 interleaved complex FP32 (the plain radix-2
  *                          comparator path), 8 B per point.
+ *   TCFFT_PREC_FP64        interleaved complex FP64, 16 B per point: the
+ *                          radix-16 blocks on the FP64 matrix core
+ *                          (v_mfma_f64_16x16x4f64), twiddles in FP64, no
+ *                          output scale (S = 0); 1D only, N = 16..4096, one
+ *                          launch; not for the server (UNSUPPORTED there).
  * Output is in natural order, in the same layout as the input.  in == out is
  * allowed (in-place).
  *
@@ -68,7 +73,8 @@ typedef enum {
 enum {
   TCFFT_PREC_FP16 = 0,        /* FP16 storage, FP16 matrix-core products, FP32 accumulation */
   TCFFT_PREC_SPLIT_FP16 = 1,  /* hi+lo FP16 pairs, compensated products (precision recovery) */
-  TCFFT_PREC_FP32_RADIX2 = 2  /* plain FP32 radix-2 Stockham, one launch per stage (comparator) */
+  TCFFT_PREC_FP32_RADIX2 = 2, /* plain FP32 radix-2 Stockham, one launch per stage (comparator) */
+  TCFFT_PREC_FP64 = 3         /* FP64 storage, FP64 matrix-core products (Sec. 7: wider types) */
 };
 
 enum {
@@ -144,20 +150,21 @@ tcfft_status tcfft_exec(tcfft_plan plan, const void* in, void* out, void* stream
  *
  * Launch structure (Sec. 3.1, Fig. 1: the plan fixes each transform's passes
  * once).  When every pass of every job is one of the variants compiled into
- * the single-launch kernel (the default FP16 and split plans of 1D N <= 2^22
- * and 2D arrays up to 2048 x 2048, 256-thread variants), the batch is ONE
- * launch per precision class: its (job, pass) segments form a work queue
- * ordered by (pass level, job), workgroups take tiles from an atomic counter,
- * and a tile of pass l of a job first waits until every tile of pass l-1 of
- * that job has finished (a wait bounded by the wall clock, 1 s by default or
- * TCFFT_FUSED_WAIT_US microseconds from the environment; a wait that runs out
- * fails the whole launch, which then drains, and is counted by
- * tcfft_fused_wait_failures).  Otherwise (other variants, real plans with a
- * fused spectrum step, the single-pass 65536 kernel) pass l of every job runs
- * after pass l-1 of every job, one persistent launch per (level, variant)
- * reading a device-resident descriptor table.  TCFFT_FUSED=0 in the
- * environment selects the second form for every batch.  Chunked FP16 plans
- * run on their own after the batch.
+ * the fused kernel (the default FP16 and split plans of 1D N <= 2^22 and 2D
+ * arrays up to 2048 x 2048, 256-thread variants), one kernel runs all
+ * variants: by default one launch per (pass level, precision, LDS class)
+ * with one workgroup per tile, pass l of every job after pass l-1 of every
+ * job (stream order).  TCFFT_FUSED=2 in the environment instead makes it one
+ * launch per (precision, LDS class) for all levels: workgroups take tiles
+ * from an atomic counter in (level, job) order and a tile of pass l of a job
+ * first waits until every tile of pass l-1 of that job has finished (a wait
+ * bounded by the wall clock, 1 s by default or TCFFT_FUSED_WAIT_US
+ * microseconds; a wait that runs out fails the whole launch, which then
+ * drains, and is counted by tcfft_fused_wait_failures).  Otherwise (other
+ * variants, real plans with a fused spectrum step, the single-pass 65536
+ * kernel, or TCFFT_FUSED=0) one persistent launch per (level, variant) reads
+ * a device-resident descriptor table.  FP32 radix-2 and FP64 jobs run as
+ * their own launches first; chunked FP16 plans run on their own.
  * Errors: as tcfft_exec; INVALID_ARG for njobs < 0, null arrays or a
  * workspace-holding plan listed twice; ALLOC when the descriptor table cannot
  * be allocated (stream-ordered).

@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # copies: the kernels consume every MFMA result on the vector ALU)
          "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-command-line-argument"]
-UNITS = ["k_row.hip", "k_col_small.hip", "k_col_256.hip", "k_col_large.hip", "k_big.hip", "k_real.hip", "k_row_real.hip", "k_plane.hip", "k_misc.hip", "k_static.hip", "k_fused.hip",
+UNITS = ["k_row.hip", "k_col_small.hip", "k_col_256.hip", "k_col_large.hip", "k_big.hip", "k_real.hip", "k_row_real.hip", "k_plane.hip", "k_misc.hip", "k_static.hip", "k_fused.hip", "k_f64.hip",
          "registry.cpp", "tcfft.cpp", "serve.cpp"]
 
 

@@ -1,31 +1,36 @@
-// Single-launch mixed batch: one kernel launch runs every pass of every job
-// of a batch (one launch per precision class).
+// Fused launches: one kernel runs any of the compiled row / column / plane
+// variants, so a mixed batch needs one launch per pass level (or one in all)
+// instead of one per (level, variant).
 //
 // The plan fixes a sequence of passes per transform once (Sec. 3.1, Fig. 1);
 // a mixed batch is the union of those sequences.  The host lays the (job,
-// pass) segments out as one work queue in the order (pass level, job), each
-// segment a run of tiles (one tile = one workgroup's share of the pass, the
-// same share the pass kernels give blockIdx.x).  The grid has one workgroup
-// per tile; a workgroup takes its tile index from an atomic counter (arrival
-// order, not blockIdx.x) and runs the segment's variant body (the same row /
-// column / plane device code as the per-variant kernels, so every result is
-// bitwise the same).  A tile of pass l of a job reads what any tile of pass
-// l-1 of that job wrote (the passes of Eq. 3 exchange data through global
-// memory only, Sec. 3.2), so it first waits until that segment's
-// finished-tile count reaches its tile count.
+// pass) segments of a launch out as one run of tiles (one tile = one
+// workgroup's share of the pass, the same share the pass kernels give
+// blockIdx.x), a workgroup per tile; the workgroup finds its segment by binary
+// search and runs the segment's variant body through a compile-time dispatch
+// table (the same row_body / col_body / plane_body code as the per-variant
+// kernels, so every result is bitwise the same).
 //
-// No deadlock: tiles are taken in queue order and a tile waits only on tiles
-// earlier in the queue, which running workgroups already hold (a pass-1 tile
-// waits on nothing; by induction every held tile finishes).  A workgroup that
-// has not started holds no tile.  Every wait is still bounded by the wall
-// clock (FusedHdr.wait_ticks): a wait that runs out sets the batch's failure
-// flag and the device-wide failure count, and from then on every workgroup
-// skips its tile, so the launch always drains.
-//
-// Visibility: each wave makes its stores visible at agent scope (release
-// fence) before the workgroup barrier, then one lane counts the tile; the
-// waiting lane reads the count with acquire semantics and every wave takes an
-// acquire fence after the barrier that follows the wait.
+// Two modes.  Level mode (ticketed = 0): one launch per pass level; tile =
+// blockIdx.x, no waits (the stream orders the levels).  Dependency mode
+// (ticketed = 1): one launch for all levels, segments in (level, job) order; a
+// tile of pass l of a job reads what any tile of pass l-1 of that job wrote
+// (the passes of Eq. 3 exchange data through global memory only, Sec. 3.2),
+// so it takes its index from an atomic counter (arrival order) and first
+// waits until that segment's finished-tile count reaches its tile count.  No
+// deadlock: a tile waits only on tiles earlier in the queue, which running
+// workgroups already hold (a pass-1 tile waits on nothing; by induction every
+// held tile finishes); a workgroup that has not started holds no tile.  Every
+// wait is still bounded by the wall clock (FusedHdr.wait_ticks): a wait that
+// runs out sets the batch's failure flag and the device-wide failure count,
+// after which the remaining dependent tiles give up at once, so the launch
+// always drains.  Visibility: each wave of a tile that is waited on makes its
+// stores visible at agent scope (release fence: on this GPU it writes back
+// the XCD's L2, whose contents other XCDs do not see) before the workgroup
+// barrier, then one lane counts the tile; the waiting lane reads the count
+// with acquire semantics and every wave takes an acquire fence after the
+// barrier that follows the wait.  Those fences and the ticket make the mode
+// slower than level mode on MI355X (measured), so level mode is the default.
 //
 // One tile per workgroup rather than a persistent loop: with a loop around the
 // variant dispatch the compiler keeps values live across variants and the
@@ -107,11 +112,11 @@ typedef const TCFFT_CONST FusedSeg CFusedSeg;
 
 __device__ unsigned g_fused_wait_failures;
 
-__device__ __forceinline__ int find_seg(CFusedSeg* segs, int nsegs, int64_t t) {
-  int lo = 0, hi = nsegs - 1;  // largest s with segs[s].start <= t
+__device__ __forceinline__ int find_seg(const TCFFT_CONST int32_t* starts, int nsegs, int t) {
+  int lo = 0, hi = nsegs - 1;  // largest s with starts[s] <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (segs[mid].start <= t) lo = mid;
+    if (starts[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -148,30 +153,36 @@ __global__ __launch_bounds__(256, SPLIT ? 1 : 2) void fused_kernel_t(const Fused
   const int64_t total = h->total;
   const int64_t ticks = h->wait_ticks;
   uint32_t* const slot = lds + h->lds_slot;  // [0] tile index, [1] wait result
-  if (threadIdx.x == 0)
-    slot[0] = (uint32_t)__hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const int64_t t = slot[0];
+  int64_t t = blockIdx.x;
+  if (h->ticketed) {  // dependency waits: tiles in arrival order
+    if (threadIdx.x == 0)
+      slot[0] = (uint32_t)__hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    t = slot[0];
+  }
   if (t >= total) return;
-  const int s = find_seg(segs, nsegs, t);
+  const int s = find_seg((const TCFFT_CONST int32_t*)h->starts, nsegs, (int)t);
   const int dep = segs[s].dep;
-  // one lane decides whether the tile runs (uniform over the workgroup)
-  if (threadIdx.x == 0)
-    slot[1] = (dep >= 0 ? wait_count(done + dep, (int)segs[dep].tiles, failed, ticks)
-                        : __hip_atomic_load(failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                  ? 1u
-                  : 0u;
-  __syncthreads();
-  const bool ok = slot[1] != 0;
-  if (dep >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  bool ok = true;
+  if (dep >= 0) {  // one lane waits and decides for the workgroup
+    if (threadIdx.x == 0)
+      slot[1] = wait_count(done + dep, (int)segs[dep].tiles, failed, ticks) ? 1u : 0u;
+    __syncthreads();
+    ok = slot[1] != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   if (ok) {
     const KParams kp = load_job(kps, segs[s].kp);
     fused_run<SPLIT>(segs[s].var, kp, t - segs[s].start, lds);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();  // every wave's stores are visible before the tile counts
-  if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(done + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // an agent-scope release writes back the XCD's L2 (the GPU's L2s are not
+  // coherent with each other): only tiles that a later tile waits on pay it
+  if (segs[s].waited) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();  // every wave's stores are visible before the tile counts
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(done + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace

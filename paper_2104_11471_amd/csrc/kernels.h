@@ -78,18 +78,19 @@ struct GroupHdr {
   int64_t reserved;
 };
 
-// Single-launch mixed batch (k_fused.hip).  The batch's passes form a queue of
-// segments, one per (job, pass), in the order (pass level, job); segment s
-// owns queue indices [start, start + tiles) and runs fused variant `var` with
+// Fused launches of mixed batches (k_fused.hip).  A launch's passes form a run
+// of segments, one per (job, pass), in the order (pass level, job); segment s
+// owns tile indices [start, start + tiles) and runs fused variant `var` with
 // descriptor kps[kp]; it may start a tile only once segment `dep` (the same
-// job's previous pass, or -1) has finished all its tiles.
+// job's previous pass, or -1) has finished all its tiles; only segments that
+// are waited on publish and count their tiles.
 struct FusedSeg {
   int64_t start;
   int64_t tiles;
   int32_t var;
   int32_t dep;
   int32_t kp;
-  int32_t pad;
+  int32_t waited;  // 1: a later segment of the launch waits on this one
 };
 static_assert(sizeof(FusedSeg) == 32, "FusedSeg layout");
 
@@ -100,11 +101,13 @@ static_assert(sizeof(FusedSeg) == 32, "FusedSeg layout");
 struct FusedHdr {
   const KParams* kps;
   const FusedSeg* segs;
+  const int32_t* starts;  // segs[s].start (compact copy for the search)
   int* ctr;
   int64_t nsegs;
   int64_t total;
   int64_t lds_slot;
   int64_t wait_ticks;  // bound of one dependency wait, wall-clock counter ticks
+  int64_t ticketed;    // 1: tiles taken from the queue head (dependency waits); 0: tile = blockIdx.x
 };
 
 // Fused variant id of `key` in the single-launch kernel, or -1.
@@ -139,6 +142,15 @@ KernelFn find_kernel(const KernelKey& key);
 size_t kernel_lds_bytes(const KernelKey& key);
 // Points (complex elements) processed by one workgroup.
 int64_t kernel_points_per_wg(const KernelKey& key);
+
+// FP64 matrix-core row pass (k_f64.hip): `batch` transforms of L complex
+// doubles (L = 16..4096, a power of two), in -> out (not in place), with the
+// FP64 table tw[m] = W_L^m (direction folded in).
+hipError_t launch_f64_row(const double2* in, double2* out, int L, int64_t batch,
+                          const double2* tw, hipStream_t s);
+// tw[m] = exp(sgn * 2 pi i m / modulus), m < count, in FP64.
+void launch_gen_twiddles_f64(double2* tw, int64_t count, int64_t modulus, double sgn,
+                             hipStream_t s);
 
 // FP32 radix-2 Stockham comparator stage.
 void launch_radix2_stage(const float2* in, float2* out, int64_t n, int64_t ns, int64_t batch,

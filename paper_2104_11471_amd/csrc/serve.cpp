@@ -283,7 +283,8 @@ tcfft_status request_sizes(tcfft_server_s* s, const tcfft_request& r, Req* q) {
   if (r.rank != 1 && r.rank != 2) return TCFFT_ERR_INVALID_ARG;
   if (r.batch <= 0 || !r.in || !r.out) return TCFFT_ERR_INVALID_ARG;
   if ((((uintptr_t)r.in) & 15) || (((uintptr_t)r.out) & 15)) return TCFFT_ERR_INVALID_ARG;
-  if (r.precision == TCFFT_PREC_FP32_RADIX2) return TCFFT_ERR_UNSUPPORTED;
+  if (r.precision == TCFFT_PREC_FP32_RADIX2 || r.precision == TCFFT_PREC_FP64)
+    return TCFFT_ERR_UNSUPPORTED;
   tcfft_status st = get_plan(s, r, &q->plan);
   if (st) return st;
   // the plan validated the shape; the batch only has the per-plan point limit

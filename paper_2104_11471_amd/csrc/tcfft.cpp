@@ -285,12 +285,15 @@ tcfft_status validate(const Desc& d) {
   if (d.rank < 1 || d.rank > 3) return TCFFT_ERR_INVALID_ARG;
   if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
   if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
-  if (d.prec < 0 || d.prec > 2) return TCFFT_ERR_INVALID_ARG;
+  if (d.prec < 0 || d.prec > 3) return TCFFT_ERR_INVALID_ARG;
   if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE |
                             TCFFT_FLAG_REAL))
     return TCFFT_ERR_INVALID_ARG;
   if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return TCFFT_ERR_INVALID_ARG;
   if (!is_pow2(d.nx) || !is_pow2(d.ny) || !is_pow2(d.nz)) return TCFFT_ERR_UNSUPPORTED;
+  if (d.prec == TCFFT_PREC_FP64 &&
+      (d.rank != 1 || d.nx > 4096 || (d.flags & TCFFT_FLAG_REAL) || d.nshards != 0))
+    return TCFFT_ERR_UNSUPPORTED;
   if (d.rank == 1) {
     if (d.nx < 16 || d.nx > ((int64_t)1 << 27)) return TCFFT_ERR_UNSUPPORTED;
   } else if (d.rank == 2) {
@@ -368,9 +371,14 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
   ps.ch = ch;
   ps.npts = d.nx * d.ny * d.nz;
   const int64_t B = d.batch;
-  const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : 8;
+  const size_t elt = d.prec == TCFFT_PREC_FP16 ? 4 : d.prec == TCFFT_PREC_FP64 ? 16 : 8;
   ps.buf_bytes = (size_t)(ps.npts * B) * elt;
   ps.in_bytes = ps.out_bytes = ps.buf_bytes;
+  if (d.prec == TCFFT_PREC_FP64) {  // one matrix-core row pass, no workspace, no scaling
+    ps.scale = 0;
+    *out = ps;
+    return TCFFT_OK;
+  }
   if (d.prec == TCFFT_PREC_FP32_RADIX2) {
     ps.ws_bytes = ps.buf_bytes;
     ps.scale = 0;
@@ -505,7 +513,7 @@ tcfft_status build_spec(const Desc& d, const Choice& ch, PlanSpec* out) {
 }
 
 std::string describe(const PlanSpec& ps) {
-  static const char* precs[] = {"fp16", "split_fp16", "fp32_radix2"};
+  static const char* precs[] = {"fp16", "split_fp16", "fp32_radix2", "fp64"};
   char b[1024];
   std::string s;
   std::snprintf(b, sizeof b,
@@ -530,6 +538,12 @@ std::string describe(const PlanSpec& ps) {
   s += b;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) {
     std::snprintf(b, sizeof b, "{\"kernel\":\"radix2_fp32\",\"stages\":%d}", ilog2(ps.npts));
+    s += b;
+  }
+  if (ps.d.prec == TCFFT_PREC_FP64) {
+    const int l = ilog2(ps.npts);
+    std::snprintf(b, sizeof b, "{\"kernel\":\"f64_row\",\"L\":%lld,\"R0\":%d,\"stages16\":%d}",
+                  (long long)ps.npts, 1 << (l % 4), l / 4);
     s += b;
   }
   for (size_t i = 0; i < ps.passes.size(); ++i) {
@@ -603,6 +617,7 @@ struct tcfft_plan_s {
   void* fimg = nullptr;     // radix-16 A operands (pass-independent: one scale variant)
   void* ws = nullptr;
   float2* r2tw = nullptr;   // FP32 radix-2 comparator: W_N^m
+  double2* f64tw = nullptr; // FP64 matrix-core plans: W_N^m, m < N
   void* zbuf = nullptr;     // real plans: the complex transform's input or output
   float2* rtw = nullptr;    // real plans: W_N^{dir k}, k <= M
   std::vector<void*> allocs;
@@ -674,6 +689,13 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
     return TCFFT_ERR_LAUNCH;
   }
   do {
+    if (d.prec == TCFFT_PREC_FP64) {
+      void* t = nullptr;
+      if ((st = dev_alloc(p, (size_t)ps.npts * sizeof(double2), &t))) break;
+      p->f64tw = (double2*)t;
+      launch_gen_twiddles_f64(p->f64tw, ps.npts, ps.npts, sgn, s);
+      break;
+    }
     if (d.prec == TCFFT_PREC_FP32_RADIX2) {
       void* t = nullptr;
       if ((st = dev_alloc(p, (size_t)(ps.npts / 2) * sizeof(float2), &t))) break;
@@ -860,6 +882,11 @@ tcfft_status exec_impl(tcfft_plan_s* p, const void* in, void* out, hipStream_t s
                        int npasses = -1) {
   const PlanSpec& ps = p->spec;
   if (ps.d.prec == TCFFT_PREC_FP32_RADIX2) return exec_r2(p, in, out, s);
+  if (ps.d.prec == TCFFT_PREC_FP64)
+    return launch_f64_row((const double2*)in, (double2*)out, (int)ps.npts, ps.d.batch, p->f64tw,
+                          s) == hipSuccess
+               ? TCFFT_OK
+               : TCFFT_ERR_LAUNCH;
   const int np = npasses < 0 ? (int)p->dp.size() : npasses;
   const int64_t B = ps.d.batch;
   // chunked execution of multi-pass plans: every pass of a chunk before the
@@ -1009,15 +1036,18 @@ struct Group {
 };
 
 // ---------------------------------------------------------------------------
-// Single-launch path (k_fused.hip): when every pass of every job has a fused
-// variant, the whole batch is one persistent launch per precision class, its
-// (job, pass) segments queued in the order (pass level, job), a job's pass
-// waiting on that job's previous pass only.  TCFFT_FUSED=0 in the environment
-// selects the per-(level, variant) launches instead; TCFFT_FUSED_WAIT_US
-// bounds one dependency wait (default 1 s).
-bool fused_on() {
+// Fused launches (k_fused.hip): when every pass of every job has a fused
+// variant, one kernel runs many variants.  TCFFT_FUSED in the environment:
+//   unset or 1  one launch per (pass level, class): no waits inside a launch,
+//               levels ordered by the stream (the default);
+//   2           one launch per class for all levels, a job's pass waiting on
+//               that job's previous pass through tile counters;
+//   0           per-(level, variant) grouped launches.
+// TCFFT_FUSED_WAIT_US bounds one dependency wait (default 1 s).
+int fused_mode() {
   const char* e = std::getenv("TCFFT_FUSED");
-  return !(e && e[0] == '0');
+  if (!e || !*e) return 1;
+  return e[0] == '0' ? 0 : e[0] == '2' ? 2 : 1;
 }
 
 int64_t fused_wait_us() {
@@ -1066,6 +1096,7 @@ tcfft_status fused_prepare(int64_t* clock_khz) {
 struct FusedClass {
   std::vector<KParams> kps;
   std::vector<FusedSeg> segs;
+  std::vector<int32_t> starts;  // segs[s].start, compact for the device's binary search
   size_t lds = 0;
   int64_t total = 0;
   size_t off = 0;  // byte offset of the class's header in the upload
@@ -1082,42 +1113,59 @@ tcfft::GraphCache::~GraphCache() {
   for (auto& kv : execs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
 }
 
-// The batch as one fused launch per precision class.  *applied is false (and
-// nothing is enqueued) when some pass has no fused variant or the batch does
-// not fit the fused kernel's limits; the caller then uses grouped launches.
-static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hipStream_t s,
-                               void* desc_arena, size_t arena_cap, tcfft::GraphCache* graphs,
-                               bool arg_upload, bool* applied) {
+// The batch as fused launches (mode 1: one per pass level and class; mode 2:
+// one per class, with dependency waits).  *applied is false (and nothing is
+// enqueued) when some pass has no fused variant or the batch does not fit the
+// fused kernel's limits; the caller then uses grouped launches.
+static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, int mode,
+                               hipStream_t s, void* desc_arena, size_t arena_cap,
+                               tcfft::GraphCache* graphs, bool arg_upload, bool* applied) {
   *applied = false;
-  FusedClass cls[2];
-  std::vector<int> last(njobs, -1);  // the job's latest segment
-  std::string sig = "fused";
+  // classes in launch order: FP16 with tiles of <= 64 KB of LDS (two
+  // workgroups per CU), FP16 with larger tiles, then the same for split data
+  // (mode 1: for each pass level in turn).  A launch's LDS is its largest
+  // variant's, so small tiles do not share a launch with 128 KB ones.  In
+  // mode 2 a job's passes must not go back to an earlier class, and a pass
+  // whose previous pass is in an earlier launch needs no wait (stream order).
+  const int NC = mode == 2 ? 4 : 4 * levels;
+  std::vector<FusedClass> cls(NC);
+  std::vector<int> last(njobs, -1), last_cls(njobs, -1);
+  std::string sig = mode == 2 ? "fused2" : "fused1";
   for (int lv = 0; lv < levels; ++lv)
     for (int j = 0; j < njobs; ++j) {
       tcfft_plan_s* p = jobs[j].plan;
-      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || lv >= (int)p->dp.size()) continue;
+      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || p->spec.d.prec == TCFFT_PREC_FP64 ||
+          lv >= (int)p->dp.size())
+        continue;
       const DevPass& dpp = p->dp[lv];
       const int var = fused_variant(dpp.spec.key);
       if (var < 0) return TCFFT_OK;
-      FusedClass& c = cls[dpp.spec.key.split ? 1 : 0];
+      const int k = (mode == 2 ? 0 : 4 * lv) + (dpp.spec.key.split ? 2 : 0) +
+                    (dpp.spec.lds > 65536 ? 1 : 0);
+      if (k < last_cls[j]) return TCFFT_OK;
+      FusedClass& c = cls[k];
       int64_t tiles = 0;
       c.kps.push_back(make_kparams(p, dpp, jobs[j].in, jobs[j].out, jobs[j].batch, jobs[j].ws, &tiles));
       FusedSeg sg{};
       sg.start = c.total;
       sg.tiles = tiles;
       sg.var = var;
-      sg.dep = last[j];
+      sg.dep = mode == 2 && last_cls[j] == k ? last[j] : -1;
+      if (sg.dep >= 0) c.segs[sg.dep].waited = 1;
       sg.kp = (int32_t)c.kps.size() - 1;
       last[j] = (int)c.segs.size();
+      last_cls[j] = k;
       c.segs.push_back(sg);
+      c.starts.push_back((int32_t)std::min<int64_t>(c.total, INT32_MAX));
       c.total += tiles;
       c.lds = std::max(c.lds, dpp.spec.lds);
       sig.append((const char*)&var, sizeof var);
+      sig.append((const char*)&k, sizeof k);
     }
   // tables: per class the header, descriptors, segments and counters (8-byte aligned)
   size_t bytes = 0;
   int64_t clock_khz = 0;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < NC; ++k) {
     FusedClass& c = cls[k];
     if (c.segs.empty()) continue;
     c.lds = (c.lds + 15) / 16 * 16;
@@ -1126,6 +1174,7 @@ static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hi
     if (st) return st;
     c.off = bytes;
     bytes += sizeof(FusedHdr) + c.kps.size() * sizeof(KParams) + c.segs.size() * sizeof(FusedSeg) +
+             (c.segs.size() * sizeof(int32_t) + 7) / 8 * 8 +
              ((2 + c.segs.size()) * sizeof(int) + 7) / 8 * 8;
   }
   if (bytes == 0) return TCFFT_OK;
@@ -1142,21 +1191,26 @@ static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hi
   }
   std::vector<uint8_t> host(bytes, 0);  // counters upload as zeros
   const int64_t ticks = fused_wait_us() * clock_khz / 1000;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < NC; ++k) {
     const FusedClass& c = cls[k];
     if (c.segs.empty()) continue;
     const size_t kb = c.kps.size() * sizeof(KParams), sb = c.segs.size() * sizeof(FusedSeg);
+    const size_t tb = (c.segs.size() * sizeof(int32_t) + 7) / 8 * 8;
     FusedHdr h{};
     h.kps = (const KParams*)(dmem + c.off + sizeof(FusedHdr));
     h.segs = (const FusedSeg*)(dmem + c.off + sizeof(FusedHdr) + kb);
-    h.ctr = (int*)(dmem + c.off + sizeof(FusedHdr) + kb + sb);
+    h.starts = (const int32_t*)(dmem + c.off + sizeof(FusedHdr) + kb + sb);
+    h.ctr = (int*)(dmem + c.off + sizeof(FusedHdr) + kb + sb + tb);
     h.nsegs = (int64_t)c.segs.size();
     h.total = c.total;
     h.lds_slot = (int64_t)(c.lds / 4);
     h.wait_ticks = ticks;
+    h.ticketed = mode == 2 ? 1 : 0;
     std::memcpy(host.data() + c.off, &h, sizeof h);
     std::memcpy(host.data() + c.off + sizeof(FusedHdr), c.kps.data(), kb);
     std::memcpy(host.data() + c.off + sizeof(FusedHdr) + kb, c.segs.data(), sb);
+    std::memcpy(host.data() + c.off + sizeof(FusedHdr) + kb + sb, c.starts.data(),
+                c.starts.size() * sizeof(int32_t));
   }
   tcfft_status st = TCFFT_OK;
   if (arg_upload) {
@@ -1173,13 +1227,13 @@ static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hi
     return g;
   };
   auto launch_all = [&](bool bucket) -> tcfft_status {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const FusedClass& c = cls[k];
       if (c.segs.empty()) continue;
       const FusedHdr* hdr = (const FusedHdr*)(dmem + c.off);
       const int64_t want = grid_of(c.total, bucket);
       void* args[] = {&hdr};
-      if (hipLaunchKernel(fused_kernel(k == 1), dim3((unsigned)std::max<int64_t>(1, want)),
+      if (hipLaunchKernel(fused_kernel((k & 2) != 0), dim3((unsigned)std::max<int64_t>(1, want)),
                           dim3(256), args, c.lds + 16, s) != hipSuccess) {
         (void)hipGetLastError();
         return TCFFT_ERR_LAUNCH;
@@ -1189,7 +1243,7 @@ static tcfft_status exec_fused(const tcfft::Job* jobs, int njobs, int levels, hi
   };
   bool use_graph = false;
   if (graphs && desc_arena) {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const int64_t g = cls[k].segs.empty() ? 0 : grid_of(cls[k].total, true);
       sig.append((const char*)&g, sizeof g);
     }
@@ -1231,17 +1285,18 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
   int levels = 0;
   for (int j = 0; j < njobs; ++j) {
     tcfft_plan_s* p = jobs[j].plan;
-    if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2) {
-      tcfft_status st = exec_r2(p, jobs[j].in, jobs[j].out, s);
+    if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || p->spec.d.prec == TCFFT_PREC_FP64) {
+      tcfft_status st = exec_impl(p, jobs[j].in, jobs[j].out, s);
       if (st) return st;
       continue;
     }
     levels = std::max(levels, (int)p->dp.size());
   }
-  if (levels > 0 && fused_on()) {
+  const int fmode = fused_mode();
+  if (levels > 0 && fmode > 0) {
     bool applied = false;
-    tcfft_status st = exec_fused(jobs, njobs, levels, s, desc_arena, arena_cap, graphs, arg_upload,
-                                 &applied);
+    tcfft_status st = exec_fused(jobs, njobs, levels, fmode, s, desc_arena, arena_cap, graphs,
+                                 arg_upload, &applied);
     if (st || applied) return st;
   }
   // every (pass level, variant) group of the batch, in launch order
@@ -1251,7 +1306,9 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     std::map<KernelKey, Group, KeyLess> lg;
     for (int j = 0; j < njobs; ++j) {
       tcfft_plan_s* p = jobs[j].plan;
-      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || lv >= (int)p->dp.size()) continue;
+      if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || p->spec.d.prec == TCFFT_PREC_FP64 ||
+          lv >= (int)p->dp.size())
+        continue;
       const DevPass& dpp = p->dp[lv];
       Group& g = lg[dpp.spec.key];
       g.fn = dpp.fn;
@@ -1458,7 +1515,7 @@ std::vector<Choice> candidates(const Desc& d) {
 
 std::vector<Choice> candidates_base(const Desc& d) {
   std::vector<Choice> out;
-  if (d.prec == TCFFT_PREC_FP32_RADIX2) return out;
+  if (d.prec == TCFFT_PREC_FP32_RADIX2 || d.prec == TCFFT_PREC_FP64) return out;
   const bool longp = d.rank == 1 && d.nx > kMaxRowL;
   if (!longp) {
     for (int sep : {0, 1}) {
@@ -1784,8 +1841,8 @@ tcfft_status tcfft_exec_passes(tcfft_plan plan, const void* in, void* out, int n
   tcfft_status st = TCFFT_OK;
   if (!plan || !in || !out || in == out || !aligned16(in) || !aligned16(out))
     st = TCFFT_ERR_INVALID_ARG;
-  else if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.real_n > 0 ||
-           plan->spec.d.nshards > 0)
+  else if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || plan->spec.d.prec == TCFFT_PREC_FP64 ||
+           plan->spec.real_n > 0 || plan->spec.d.nshards > 0)
     st = TCFFT_ERR_UNSUPPORTED;
   else if (npasses < 1 || npasses > (int)plan->dp.size())
     st = TCFFT_ERR_INVALID_ARG;
@@ -1878,6 +1935,7 @@ size_t tcfft_plan_workspace_bytes(tcfft_plan plan) {
 int tcfft_plan_num_launches(tcfft_plan plan) {
   if (!plan) return -1;
   if (plan->spec.d.prec == TCFFT_PREC_FP32_RADIX2) return ilog2(plan->spec.npts);
+  if (plan->spec.d.prec == TCFFT_PREC_FP64) return 1;
   return (int)plan->spec.passes.size() + (plan->spec.real_n > 0 && !plan->spec.real_fused ? 1 : 0);
 }
 

@@ -19,12 +19,13 @@ INVERSE = 1
 PREC_FP16 = 0
 PREC_SPLIT_FP16 = 1
 PREC_FP32_RADIX2 = 2
+PREC_FP64 = 3
 FLAG_NO_SCALE = 1
 FLAG_NO_GRAPH = 2
 FLAG_TUNE = 4
 FLAG_REAL = 8
 _PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_FP16,
-         "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2}
+         "fp32_radix2": PREC_FP32_RADIX2, "fp32": PREC_FP32_RADIX2, "fp64": PREC_FP64}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "no device", 4: "alloc",
           5: "launch", 6: "internal", 7: "timeout", 8: "cancelled"}
@@ -178,7 +179,8 @@ class Plan:
       * fp16: ``float16`` of shape ``(batch, *dims, 2)`` (interleaved re, im);
       * split: ``float16`` of shape ``(2, batch, *dims, 2)`` -- hi plane then lo
         plane, value = hi + 2^-11 lo;
-      * fp32_radix2: ``float32`` of shape ``(batch, n, 2)``.
+      * fp32_radix2: ``float32`` of shape ``(batch, n, 2)``;
+      * fp64: ``float64`` of shape ``(batch, n, 2)`` (FP64 matrix-core path).
     The output holds DFT(x) * 2^-scale_log2 in the same layout.
 
     Real plans (``flags`` with FLAG_REAL, 1D, N = 2M): the real side is
@@ -260,6 +262,8 @@ class Plan:
 
     def dtype(self):
         import torch
+        if self.precision == PREC_FP64:
+            return torch.float64
         return torch.float32 if self.precision == PREC_FP32_RADIX2 else torch.float16
 
     def empty(self, device=None):

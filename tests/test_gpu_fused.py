@@ -1,7 +1,8 @@
-"""Single-launch mixed batches (k_fused.hip) on the GPU: bitwise equality with
-the per-(level, variant) launches and with each job alone, parity with the
-oracle, HIP-graph capture and replay, and the bounded dependency wait forced
-to give up from the host."""
+"""Fused mixed batches (k_fused.hip) on the GPU, in both modes (one launch per
+pass level and class; one launch per class with per-job dependency waits):
+bitwise equality with the per-(level, variant) launches and with each job
+alone, parity with the oracle, HIP-graph capture and replay, and the bounded
+dependency wait forced to give up from the host."""
 import os
 
 import numpy as np
@@ -61,7 +62,8 @@ def _setup(jobs):
     return plans, xs
 
 
-def test_fused_batch_bitwise_and_parity():
+@pytest.mark.parametrize("mode", ["1", "2"])
+def test_fused_batch_bitwise_and_parity(mode):
     import torch
     from paper_2104_11471_amd import tcfft
     plans, xs = _setup(JOBS)
@@ -69,9 +71,10 @@ def test_fused_batch_bitwise_and_parity():
     grouped = [torch.empty_like(x) for x in xs]
     alone = [torch.empty_like(x) for x in xs]
     before = tcfft.fused_wait_failures()
-    log(f"fused batch: {len(JOBS)} jobs")
-    tcfft.exec_many(plans, xs, fused)
-    torch.cuda.synchronize()
+    log(f"fused batch (TCFFT_FUSED={mode}): {len(JOBS)} jobs")
+    with _Env(TCFFT_FUSED=mode):
+        tcfft.exec_many(plans, xs, fused)
+        torch.cuda.synchronize()
     log("grouped batch (TCFFT_FUSED=0)")
     with _Env(TCFFT_FUSED=0):
         tcfft.exec_many(plans, xs, grouped)
@@ -100,7 +103,8 @@ def test_fused_batch_bitwise_and_parity():
         assert e.max() < tol, (i, JOBS[i], float(e.max()))
 
 
-def test_fused_static_graph_capture_replays():
+@pytest.mark.parametrize("mode", ["1", "2"])
+def test_fused_static_graph_capture_replays(mode):
     """tcfft_exec_many_static (descriptor tables written by kernels from their
     arguments, no allocation, no memset) captured into one HIP graph; each
     replay, with fresh inputs copied in and eager work between replays,
@@ -112,15 +116,16 @@ def test_fused_static_graph_capture_replays():
     plans, xs = _setup(jobs)
     outs = [torch.empty_like(x) for x in xs]
     ref = [torch.empty_like(x) for x in xs]
-    tcfft.exec_many(plans, xs, outs, static=True)  # eager first: one-time set-up outside capture
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        with torch.cuda.graph(g, stream=s):
-            tcfft.exec_many(plans, xs, outs, static=True)
-    torch.cuda.synchronize()
+    with _Env(TCFFT_FUSED=mode):
+        tcfft.exec_many(plans, xs, outs, static=True)  # eager first: one-time set-up outside capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                tcfft.exec_many(plans, xs, outs, static=True)
+        torch.cuda.synchronize()
     for rep in range(4):
         log(f"graph replay {rep}")
         for i, (dims, batch, prec) in enumerate(jobs):
@@ -136,9 +141,10 @@ def test_fused_static_graph_capture_replays():
 
 
 def test_fused_wait_bound_forced_from_host():
-    """A zero wait bound (TCFFT_FUSED_WAIT_US=0) makes the first pass-2 tile that
-    arrives before its pass 1 has finished give up: the launch drains, the
-    failure is counted, and the next batch with the default bound is right."""
+    """Dependency mode (TCFFT_FUSED=2) with a zero wait bound
+    (TCFFT_FUSED_WAIT_US=0): the first pass-2 tile that arrives before its
+    pass 1 has finished gives up, the launch drains, the failure is counted,
+    and the next batch with the default bound is right."""
     import torch
     from paper_2104_11471_amd import tcfft
     jobs = [((65536,), 64, "fp16")]
@@ -146,13 +152,14 @@ def test_fused_wait_bound_forced_from_host():
     out = torch.empty_like(xs[0])
     ref = torch.empty_like(xs[0])
     before = tcfft.fused_wait_failures()
-    with _Env(TCFFT_FUSED_WAIT_US=0):
+    with _Env(TCFFT_FUSED=2, TCFFT_FUSED_WAIT_US=0):
         tcfft.exec_many(plans, xs, [out])
         torch.cuda.synchronize()
     after = tcfft.fused_wait_failures()
     log(f"wait failures {before} -> {after}")
     assert after == before + 1
-    tcfft.exec_many(plans, xs, [out])
+    with _Env(TCFFT_FUSED=2):
+        tcfft.exec_many(plans, xs, [out])
     plans[0](xs[0], ref)
     torch.cuda.synchronize()
     assert tcfft.fused_wait_failures() == after

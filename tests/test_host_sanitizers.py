@@ -18,7 +18,7 @@ OBJ = os.path.join(ROOT, "paper_2104_11471_amd", "_build")
 ROCM = "/opt/rocm"
 CXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 DEVICE_UNITS = ["k_row", "k_col_small", "k_col_256", "k_col_large", "k_big", "k_real",
-                "k_row_real", "k_plane", "k_misc", "k_static", "k_fused", "registry"]
+                "k_row_real", "k_plane", "k_misc", "k_static", "k_fused", "k_f64", "registry"]
 SAN = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all"]
 
 
