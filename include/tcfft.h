@@ -79,7 +79,8 @@ enum {
 
 enum {
   TCFFT_FLAG_NO_SCALE = 1u, /* S = 0: literally unnormalised (may overflow FP16 for large N) */
-  TCFFT_FLAG_NO_GRAPH = 2u, /* reserved: never capture the pass sequence in a HIP graph */
+  TCFFT_FLAG_NO_GRAPH = 2u, /* serving: a batch holding this plan is launched directly, never replayed
+                               from a captured HIP graph (use_graphs) */
   TCFFT_FLAG_TUNE = 4u,     /* time every planner candidate on the device and keep the fastest */
   TCFFT_FLAG_REAL = 8u      /* real data: FORWARD is real-to-complex, INVERSE complex-to-real */
 };
@@ -245,8 +246,10 @@ tcfft_status tcfft_exec_shard(tcfft_plan plan, int step, const void* in, void* o
 int tcfft_shard_dry_run(int64_t n, int64_t batch, int dir, int precision, int nshards, int shard,
                         unsigned flags, char* buf, size_t len);
 
-/* Releases the plan and its device memory (synchronises the device first).
- * NULL is accepted.  Errors: none besides INTERNAL. */
+/* Releases the plan and its device memory (synchronises the device first:
+ * the plan's tables may be read by work on any stream, and freeing device
+ * memory waits for the device anyway).  NULL is accepted.  Errors: none
+ * besides INTERNAL. */
 tcfft_status tcfft_plan_destroy(tcfft_plan plan);
 
 /* S such that out = DFT(in) * 2^-S (0 for NO_SCALE and the FP32 path); -1 for NULL. */

@@ -626,7 +626,8 @@ __device__ __forceinline__ void row_stage_fused(const KParams& kp, uint32_t* lds
 }
 
 // ---------------------------------------------------------------------------
-// Radix-R0 x radix-16 block entirely on the matrix core (FP16 data).  With the
+// Radix-R0 x radix-16 block entirely on the matrix core (FP16 data; used by
+// the column passes, see col_fused_mx).  With the
 // digits n = d P0 + m P + lo of a line (P0 = 16 P) and the DIF order of the
 // fused stage, radix-R0 output k and radix-16 output k1 are
 //   Y[k][k1][lo] = W_L^{(k + R0 k1) lo} *
@@ -689,111 +690,11 @@ __device__ __forceinline__ void mfma_rot(const FOpsMx& f, u4 b, f4& yr, f4& yi) 
   yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai, bh, yi, 0, 0, 0);
 }
 
-// Used for the 16384-point pass (R0 = 4): the four-fold matrix-core work of the
-// radix-4 sum there replaces the heaviest vector-ALU stage of the library; for
-// shorter lines it measured no faster than the vector-ALU radix-R0 stage.
-template <class G>
-struct RowFusedMx {
-  static constexpr bool value = RowFused<G>::value && (G::R0 == 2 || G::R0 == 4) &&
-                                G::L >= 16384;
-};
-
 // Radix-R0 sum over d for output k of the fused block (compile-time k, d).
 template <int R0, int K, int D = 0>
 __device__ __forceinline__ void mfma_rsum(const FOpsMx& f, const u4 (&b)[R0], f4& yr, f4& yi) {
   mfma_rot<((K * D) % R0) * (4 / R0)>(f, b[D], yr, yi);
   if constexpr (D + 1 < R0) mfma_rsum<R0, K, D + 1>(f, b, yr, yi);
-}
-
-template <class G, int K = 0>
-__device__ __forceinline__ void row_fused_mx_k(const KParams& kp, uint32_t* lds,
-                                               const u4 (&hh)[G::R0][4], int tau, int lo0) {
-  constexpr int L = G::L, R0 = G::R0;
-  constexpr int P = RowFused<G>::P, P0 = 16 * P;
-  const int g = (threadIdx.x & 63) >> 4;
-  const int k = kp.sgn < 0.f ? K : (R0 - K) % R0;  // the output this block is
-  const FOpsMx fm = load_fops_mx(kp.fimg2, K);
-  float2 st[4];  // W_L^e, e = k + R0 (4g + j)
-#pragma unroll
-  for (int j = 0; j < 4; ++j) st[j] = tld(kp.tw, k + R0 * (4 * g + j));
-  uint32_t oh[4][4];  // [t][j]
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    u4 b[R0];
-#pragma unroll
-    for (int d = 0; d < R0; ++d) b[d] = u4{hh[d][0][t], hh[d][1][t], hh[d][2][t], hh[d][3][t]};
-    f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-    mfma_rsum<R0, K>(fm, b, yr, yi);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      // W_L^{e (lo0 + t)} = W_L^{e lo0} (W_L^e)^t, e = k + R0 (4g + j)
-      float2 w = tld(kp.tw, (k + R0 * (4 * g + j)) * lo0);
-#pragma unroll
-      for (int u = 0; u < t; ++u) w = cmul(w, st[j]);
-      const float2 z = cmul(make_float2(yr[j], yi[j]), w);
-      oh[t][j] = pack(z.x, z.y);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int p = tau * L + k * P0 + (4 * g + j) * P + lo0;
-    lds_st4(lds, p, u4{oh[0][j], oh[1][j], oh[2][j], oh[3][j]});
-  }
-  if constexpr (K + 1 < R0) row_fused_mx_k<G, K + 1>(kp, lds, hh, tau, lo0);
-}
-
-// Inputs of the fused matrix-core block: per iteration, rows 4g..4g+3 of every
-// radix-R0 digit d at 4 consecutive low indices lo0..lo0+3.
-template <class G>
-struct RowMxRegs {
-  u4 hh[RowFused<G>::ITF][G::R0][4];  // [it][d][row i]
-};
-
-template <class G, bool SRCL = false>
-__device__ __forceinline__ void row_fused_mx_load(const KParams& kp, const uint32_t* lds,
-                                                  int valid, int64_t g0, RowMxRegs<G>& r) {
-  constexpr int L = G::L, R0 = G::R0;
-  using F = RowFused<G>;
-  constexpr int P = F::P, P0 = 16 * P, ITF = F::ITF;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-#pragma unroll
-  for (int it = 0; it < ITF; ++it) {
-    const int sq = (wave * ITF + it) * 16 + c16;
-    const int tau = sq / (P / 4);
-    const int lo0 = 4 * (sq % (P / 4));
-    const int taul = (!SRCL && G::TPB > 1 && tau >= valid) ? 0 : tau;
-#pragma unroll
-    for (int d = 0; d < R0; ++d)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int p = taul * L + d * P0 + (4 * g + i) * P + lo0;
-        if constexpr (SRCL) r.hh[it][d][i] = lds_ld4(lds, p);
-        else r.hh[it][d][i] = row_ld4<G>(kp.in + g0 + p);
-      }
-  }
-}
-
-template <class G>
-__device__ __forceinline__ void row_fused_mx_compute(const KParams& kp, uint32_t* lds,
-                                                     const RowMxRegs<G>& r) {
-  using F = RowFused<G>;
-  constexpr int P = F::P, ITF = F::ITF;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c16 = lane & 15;
-#pragma unroll
-  for (int it = 0; it < ITF; ++it) {
-    const int sq = (wave * ITF + it) * 16 + c16;
-    row_fused_mx_k<G>(kp, lds, r.hh[it], sq / (P / 4), 4 * (sq % (P / 4)));
-  }
-}
-
-template <class G, bool SRCL = false>
-__device__ __forceinline__ void row_stage_fused_mx(const KParams& kp, uint32_t* lds, int valid,
-                                                   int64_t g0) {
-  RowMxRegs<G> r;
-  row_fused_mx_load<G, SRCL>(kp, lds, valid, g0, r);
-  row_fused_mx_compute<G>(kp, lds, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,11 +958,7 @@ __device__ __forceinline__ void row_body(const KParams& kp, int64_t wg, uint32_t
     real_pre<G, SPLIT>(kp, lds, valid, t0);
     __syncthreads();
   }
-  if constexpr (!SPLIT && RowFusedMx<G>::value) {
-    row_stage_fused_mx<G, SRCL>(kp, lds, valid, g0);
-    __syncthreads();
-    row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
-  } else if constexpr (RowFused<G>::value) {
+  if constexpr (RowFused<G>::value) {
     row_stage_fused<G, SPLIT, SRCL>(kp, lds, valid, g0, f);
     __syncthreads();
     row_stages_from<G, G::S - 2, SPLIT, TT, KEEP>(kp, lds, valid, g0, f);
@@ -1498,9 +1395,11 @@ __device__ __forceinline__ void col_stage_fused(const KParams& kp, uint32_t* lds
   }
 }
 
-// Column-pass form of row_stage_fused_mx: the 4 tiles of a lane are 4
-// adjacent columns at one low index lo, so the twiddle W_L^{(k + R0 k1) lo} is
-// one lookup per output row.
+// The matrix-core radix-R0 x radix-16 block in a column pass: the 4 tiles of a
+// lane are 4 adjacent columns at one low index lo, so the twiddle
+// W_L^{(k + R0 k1) lo} is one lookup per output row.  (Row passes keep the
+// vector-ALU radix-R0 stage: for the 16384-point pass the block's four-fold
+// matrix-core work measured slower under sustained load, 239 against 230 us.)
 template <class G>
 struct ColFusedMx {
   static constexpr bool value = ColFused<G>::value && (G::R0 == 2 || G::R0 == 4);

@@ -736,7 +736,7 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
       }
       void* t = nullptr;
       const int r0 = r0_of(sp.key.L);
-      if (r0 == 2 || r0 == 4) {
+      if ((r0 == 2 || r0 == 4) && sp.key.kind == K_COL) {  // the column passes' matrix-core block
         if ((st = dev_alloc(p, (size_t)r0 * 256 * 16, &dpp.fimg2))) break;
         // both stages' scales: 2^-1 (radix 2 or 4) and 2^-2 (radix 16)
         launch_gen_fimg_r(dpp.fimg2, r0, sgn, noscale ? 1.0 : 0.125, s);
@@ -1283,6 +1283,8 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
                                       void* desc_arena, size_t arena_cap,
                                       tcfft::GraphCache* graphs, bool arg_upload) {
   int levels = 0;
+  for (int j = 0; j < njobs; ++j)  // plans created with NO_GRAPH keep the batch out of graphs
+    if (jobs[j].plan->spec.d.flags & TCFFT_FLAG_NO_GRAPH) graphs = nullptr;
   for (int j = 0; j < njobs; ++j) {
     tcfft_plan_s* p = jobs[j].plan;
     if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || p->spec.d.prec == TCFFT_PREC_FP64) {
