@@ -250,7 +250,7 @@ def fp64_workloads(stream) -> dict:
     """FP64 matrix-core path: batched 1D N = 4096 x 32768 and 256 x 524288
     (2^27 points, 2 GiB of complex FP64 each way): time, algorithmic HBM
     bytes (16 B read + 16 B written per point) and the FP64 matrix-core work
-    (16 v_mfma_f64_16x16x4f64 = 32768 flops per 256 points per radix-16
+    (12 v_mfma_f64_16x16x4f64 = 24576 flops per 256 points per radix-16
     stage) against the 78.6 TFLOP/s FP64 peak; row-0 accuracy against the
     oracle.  Not part of `value`."""
     import torch
@@ -267,7 +267,7 @@ def fp64_workloads(stream) -> dict:
         y0 = yd[0].cpu().numpy()
         err = float(oracle.rel_l2(y0[:, 0] + 1j * y0[:, 1], oracle.fft(z[0], -1), axis=None))
         stages = int(round(math.log2(n))) // 4
-        mfma_flop = 128.0 * stages * TOTAL_POINTS
+        mfma_flop = 96.0 * stages * TOTAL_POINTS
         key = f"1d_{n}x{batch}_fp64"
         out[key] = {"us": round(dt * 1e6, 1),
                     "gbs_alg": round(32.0 * TOTAL_POINTS / dt / 1e9, 1),
