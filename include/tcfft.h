@@ -395,9 +395,10 @@ int64_t tcfft_server_now_ns(void);
 const char* tcfft_status_string(tcfft_status s);
 
 /*
- * Diagnostics of the single-launch batch path (tcfft_exec_many): the number of
- * dependency waits, on the current device since the library was loaded, that
- * ran past their bound and failed their launch.  Synchronous (a device copy);
+ * Diagnostics of the fused batch path in its dependency mode (tcfft_exec_many
+ * with TCFFT_FUSED=2): the number of dependency waits, on the current device
+ * since the library was loaded, that ran past their bound and failed their
+ * launch.  Synchronous (a device copy);
  * *count is untouched on error.  Errors: INVALID_ARG (null), NO_DEVICE.
  */
 tcfft_status tcfft_fused_wait_failures(unsigned* count);

@@ -215,14 +215,11 @@ hipError_t launch_f64_row(const double2* in, double2* out, int L, int64_t batch,
                           const double2* tw, hipStream_t s) {
   // persistent grid for the prefetching variants: two resident workgroups per
   // CU (64 KB of LDS each) stride over the tiles
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      return hipErrorInvalidDevice;
-    ncu = n;
-  }
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu <= 0)
+    return hipErrorInvalidDevice;
   const int tpb = F64_PTS / L;
   const int64_t ntiles = (batch + tpb - 1) / tpb;
   const bool pref = L != 128 && L != 2048;  // R0 <= 4: the persistent kernels

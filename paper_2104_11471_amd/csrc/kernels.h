@@ -110,9 +110,9 @@ struct FusedHdr {
   int64_t ticketed;    // 1: tiles taken from the queue head (dependency waits); 0: tile = blockIdx.x
 };
 
-// Fused variant id of `key` in the single-launch kernel, or -1.
+// Fused variant id of `key` in the fused kernels, or -1.
 int fused_variant(const KernelKey& key);
-// The single-launch kernel of one precision class (FP16 or split).
+// The fused kernel of one precision (FP16 or split).
 const void* fused_kernel(bool split);
 // Device-wide count of dependency waits that gave up (read with a copy).
 hipError_t fused_wait_failures(unsigned* count);

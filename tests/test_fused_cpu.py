@@ -1,7 +1,7 @@
-"""Coverage of the single-launch batch kernel (no device): every pass of the
-default plans of the serving population and of the common 1D / 2D sizes is
-one of its compiled variants, so tcfft_exec_many runs such batches as one
-launch per precision class."""
+"""Coverage of the fused batch kernels (no device): every pass of the default
+plans of the serving population and of the common 1D / 2D sizes is one of
+their compiled variants, so tcfft_exec_many runs such batches as fused
+launches (one per pass level, precision and LDS class)."""
 import pytest
 
 from paper_2104_11471_amd import tcfft
