@@ -79,8 +79,6 @@ enum {
 
 enum {
   TCFFT_FLAG_NO_SCALE = 1u, /* S = 0: literally unnormalised (may overflow FP16 for large N) */
-  TCFFT_FLAG_NO_GRAPH = 2u, /* serving: a batch holding this plan is launched directly, never replayed
-                               from a captured HIP graph (use_graphs) */
   TCFFT_FLAG_TUNE = 4u,     /* time every planner candidate on the device and keep the fastest */
   TCFFT_FLAG_REAL = 8u      /* real data: FORWARD is real-to-complex, INVERSE complex-to-real */
 };

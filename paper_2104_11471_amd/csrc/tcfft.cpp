@@ -286,7 +286,7 @@ tcfft_status validate(const Desc& d) {
   if (d.batch <= 0) return TCFFT_ERR_INVALID_ARG;
   if (d.dir != TCFFT_FORWARD && d.dir != TCFFT_INVERSE) return TCFFT_ERR_INVALID_ARG;
   if (d.prec < 0 || d.prec > 3) return TCFFT_ERR_INVALID_ARG;
-  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_NO_GRAPH | TCFFT_FLAG_TUNE |
+  if (d.flags & ~(unsigned)(TCFFT_FLAG_NO_SCALE | TCFFT_FLAG_TUNE |
                             TCFFT_FLAG_REAL))
     return TCFFT_ERR_INVALID_ARG;
   if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return TCFFT_ERR_INVALID_ARG;
@@ -1283,8 +1283,6 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
                                       void* desc_arena, size_t arena_cap,
                                       tcfft::GraphCache* graphs, bool arg_upload) {
   int levels = 0;
-  for (int j = 0; j < njobs; ++j)  // plans created with NO_GRAPH keep the batch out of graphs
-    if (jobs[j].plan->spec.d.flags & TCFFT_FLAG_NO_GRAPH) graphs = nullptr;
   for (int j = 0; j < njobs; ++j) {
     tcfft_plan_s* p = jobs[j].plan;
     if (p->spec.d.prec == TCFFT_PREC_FP32_RADIX2 || p->spec.d.prec == TCFFT_PREC_FP64) {

@@ -21,7 +21,6 @@ PREC_SPLIT_FP16 = 1
 PREC_FP32_RADIX2 = 2
 PREC_FP64 = 3
 FLAG_NO_SCALE = 1
-FLAG_NO_GRAPH = 2
 FLAG_TUNE = 4
 FLAG_REAL = 8
 _PREC = {"fp16": PREC_FP16, "split": PREC_SPLIT_FP16, "split_fp16": PREC_SPLIT_FP16,

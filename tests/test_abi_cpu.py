@@ -260,3 +260,10 @@ def test_plan_3d_rejects(tc, dims, status):
     with pytest.raises(tc.TcfftError) as e:
         tc.dry_run((64, 64, 64), 1, precision="fp32")
     assert e.value.status == 2
+
+
+def test_unknown_flag_bits_are_rejected(tc):
+    for bad in (2, 16, 1 << 31):
+        with pytest.raises(tc.TcfftError) as e:
+            tc.dry_run((256,), 1, flags=bad)
+        assert e.value.status == 1  # INVALID_ARG
