@@ -57,6 +57,15 @@ def time_launches(fn, reps: int, stream, warm: int = 5) -> float:
     return start.elapsed_time(end) / 1e3 / reps
 
 
+def time_trials(fn, stream, min_s: float = 0.1, trials: int = 5) -> float:
+    """Median over `trials` of the mean duration (s) of R back-to-back calls,
+    R chosen so that each trial times at least `min_s` (after 5 warm calls)."""
+    est = time_launches(fn, 3, stream, warm=5)
+    reps = max(10, int(math.ceil(min_s / max(est, 1e-7))))
+    res = sorted(time_launches(fn, reps, stream, warm=0) for _ in range(trials))
+    return res[len(res) // 2]
+
+
 def time_cold(fn, reps: int, stream, flush) -> float:
     """Average duration (s) of fn() with the memory-side cache flushed before
     each call (a 512 MiB buffer rewritten between the timed calls)."""
@@ -477,7 +486,7 @@ def run_workloads(specs, reps: int, stream) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -563,11 +572,12 @@ def main():
     rng = np.random.default_rng(1)
     for n in SIZES:
         batch = TOTAL_POINTS // n
-        # the accuracy check of the previous size leaves the GPU idle for
-        # seconds: bring the clocks back up before timing
+        # 5 trials of >= 100 ms of back-to-back launches each, median (the
+        # accuracy check of the previous size leaves the GPU idle for seconds:
+        # 20 untimed launches bring the clocks back up first)
         for _ in range(20):
             plans[n](xd[n], yd[n], stream=stream)
-        dt = time_launches(lambda: plans[n](xd[n], yd[n], stream=stream), 20, stream)
+        dt = time_trials(lambda: plans[n](xd[n], yd[n], stream=stream), stream)
         emax, erms, eq5, ns = accuracy_sample(plans[n], xd[n], yd[n], xs[n][0], xs[n][1], rng)
         per[n] = {"us": round(dt * 1e6, 2), "gflops": round(flops(n, batch) / dt / 1e9, 1),
                   "gbs_alg": round(8.0 * TOTAL_POINTS / dt / 1e9, 1),
