@@ -215,7 +215,7 @@ def other_workloads(stream) -> dict:
             yd = torch.empty_like(xd)
             p = tcfft.Plan(dims, batch, precision=prec, flags=tcfft.FLAG_TUNE)
             p(xd, yd, stream=stream)
-            dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
+            dt = time_trials(lambda: p(xd, yd, stream=stream), stream)
             dt_cold = None
             if kind == "1d":  # 64 MiB of data fits the 256 MB memory-side cache: cold variant too
                 with torch.cuda.stream(stream):
@@ -272,7 +272,7 @@ def fp64_workloads(stream) -> dict:
         xd = torch.from_numpy(np.stack([z.real, z.imag], -1)).cuda()
         yd = torch.empty_like(xd)
         p = tcfft.Plan((n,), batch, tcfft.FORWARD, "fp64")
-        dt = time_launches(lambda: p(xd, yd, stream=stream), 10, stream)
+        dt = time_trials(lambda: p(xd, yd, stream=stream), stream)
         y0 = yd[0].cpu().numpy()
         err = float(oracle.rel_l2(y0[:, 0] + 1j * y0[:, 1], oracle.fft(z[0], -1), axis=None))
         stages = int(round(math.log2(n))) // 4
@@ -315,7 +315,7 @@ def real_workloads(stream) -> dict:
             xd = torch.from_numpy(host).cuda().reshape(p.in_shape())
             yd = torch.empty(p.out_shape(), dtype=torch.float16, device=xd.device)
             p(xd, yd, stream=stream)
-            dt = time_launches(lambda: p(xd, yd, stream=stream), 5, stream)
+            dt = time_trials(lambda: p(xd, yd, stream=stream), stream)
             y = yd.cpu().numpy().astype(np.float64)
             if split:
                 x0 = host[0][0].astype(np.float64) + 2.0 ** -11 * host[1][0].astype(np.float64)
@@ -383,7 +383,7 @@ def mixed_batch_leg(stream, single_pass: bool = False) -> dict:
         try:
             for _ in range(3):
                 tcfft.exec_many(plans, xs, ys, stream=stream)
-            dt = time_launches(lambda: tcfft.exec_many(plans, xs, ys, stream=stream), 50, stream)
+            dt = time_trials(lambda: tcfft.exec_many(plans, xs, ys, stream=stream), stream)
         finally:
             if old is None:
                 os.environ.pop("TCFFT_FUSED", None)
