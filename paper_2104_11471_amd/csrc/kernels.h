@@ -124,6 +124,7 @@ struct KernelFns {
   KernelFn single = nullptr;
   MultiFn multi = nullptr;
   bool persistent = false;  // `single` strides over tiles: any grid up to the tile count works
+  bool multi_one = false;   // `multi` runs one tile per workgroup: its grid is the tile count
 };
 
 // Looks up the compiled variant for `key`; false when it is not compiled.

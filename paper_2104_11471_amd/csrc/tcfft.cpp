@@ -1366,7 +1366,9 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     for (size_t i = 0; i < G; ++i) {
       const Group& g = groups[i];
       const GroupHdr* hdr = (const GroupHdr*)(dmem + i * sizeof(GroupHdr));
-      const int64_t want = full_grid ? g.persist : std::min<int64_t>(g.prefix.back(), g.persist);
+      const int64_t want = g.fn.multi_one ? g.prefix.back()  // one tile per workgroup
+                           : full_grid    ? g.persist
+                                          : std::min<int64_t>(g.prefix.back(), g.persist);
       const unsigned grid = (unsigned)std::max<int64_t>(1, want);
       void* args[] = {&hdr};
       if (hipLaunchKernel((const void*)g.fn.multi, dim3(grid), dim3(g.nt), args, g.lds, s) !=
@@ -1385,7 +1387,11 @@ tcfft_status tcfft_internal_exec_jobs(const tcfft::Job* jobs, int njobs, hipStre
     // a sequence is captured only once it recurs (capture costs far more
     // than a few launches)
     sig.assign((const char*)keys.data(), keys.size() * sizeof(KernelKey));
-    use_graph = graphs->execs.count(sig) > 0 || ++graphs->seen[sig] >= graphs->capture_after;
+    // a one-tile-per-workgroup group's grid follows its tile count: such
+    // batches are launched directly
+    bool one = false;
+    for (const Group& g : groups) one = one || g.fn.multi_one;
+    use_graph = !one && (graphs->execs.count(sig) > 0 || ++graphs->seen[sig] >= graphs->capture_after);
   }
   if (use_graph) {
     auto it = graphs->execs.find(sig);

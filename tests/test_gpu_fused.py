@@ -53,6 +53,9 @@ class _Env:
 def _setup(jobs):
     import torch
     from paper_2104_11471_amd import tcfft
+    # default plans: choices an earlier test tuned (the cache is per process)
+    # may use variants outside the fused table
+    tcfft.tune_cache_clear()
     plans, xs = [], []
     for i, (dims, batch, prec) in enumerate(jobs):
         p = tcfft.Plan(dims, batch, precision=prec)

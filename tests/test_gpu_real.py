@@ -158,6 +158,29 @@ def test_real_grouped_matches_single(tc):
         assert torch.equal(a.view(torch.int16), o.view(torch.int16))
 
 
+def test_real_split_grouped_matches_single(tc):
+    """Split real plans with the fused epilogue / prologue in one grouped call
+    (their grouped kernels run one tile per workgroup) give each job's
+    single-exec bits, beside an FP16 real plan of the same size."""
+    import torch
+    jobs = [(8192, 5, tc.FORWARD, "split"), (1024, 37, tc.INVERSE, "split"),
+            (16384, 2, tc.FORWARD, "split"), (256, 300, tc.INVERSE, "split"),
+            (8192, 3, tc.FORWARD, "fp16")]
+    plans, xs = [], []
+    for i, (n, b, d, prec) in enumerate(jobs):
+        p = tc.Plan((n,), b, d, prec, flags=tc.FLAG_REAL)
+        assert p.describe()["real_kernel"] == "fused"
+        host = real_input(n, b, prec, 10 + i)[0] if d == tc.FORWARD else spectrum_input(n, b, prec, 10 + i)[0]
+        plans.append(p)
+        xs.append(torch.from_numpy(np.ascontiguousarray(host)).cuda().reshape(p.in_shape()))
+    singles = [p(x) for p, x in zip(plans, xs)]
+    outs = [p.empty_out() for p in plans]
+    tc.exec_many(plans, xs, outs)
+    torch.cuda.synchronize()
+    for i, (a, o) in enumerate(zip(singles, outs)):
+        assert torch.equal(a.view(torch.int16), o.view(torch.int16)), jobs[i]
+
+
 def test_real_rejects_overlap(tc):
     """Lines of M and M + 1 words cannot be rewritten in place: overlapping
     buffers of a real plan are an argument error, nothing is launched."""
