@@ -24,6 +24,7 @@ namespace tcfft {
     } else {                                                                        \
       out->single = (KernelFn)col_kernel<L_, R_, C_, N_, false, X_, T_>;             \
       out->multi = (MultiFn)col_kernel_multi<L_, R_, C_, N_, false, X_, T_>;         \
+      out->persistent = ColPipe<ColGeom<L_, R_, C_, N_>, false, T_>::value;          \
     }                                                                                \
     return true;                                                                     \
   }

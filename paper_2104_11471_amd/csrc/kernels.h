@@ -12,7 +12,7 @@ struct KParams {
   uint32_t* out;
   int64_t in_plane;        // split: offset of the lo plane from `in` (else 0)
   int64_t out_plane;
-  int64_t ntrans;          // row kernel: number of transforms
+  int64_t ntrans;          // row kernel: number of transforms; column kernel: number of tiles
   const float2* tw;        // W_L^m, m in [0, L)   (direction folded in)
   const void* fimg;        // radix-16 A-operand images (4 x 64 lanes x 8 halves)
   float r0scale;           // scale of the radix-2/4/8 stage (power of two)

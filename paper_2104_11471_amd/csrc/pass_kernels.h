@@ -1127,35 +1127,81 @@ __device__ __forceinline__ float2 xtwiddle(const KParams& kp, uint32_t ci, uint3
   return cmul(a, b);
 }
 
-template <class G, int P, bool SRCG, bool SPLIT, bool XTW, bool TSTORE>
-__device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, const ColCtx& cx,
-                                            const FOps& f) {
-  constexpr int L = G::L, R0 = G::R0, S = G::S, C = G::C;
-  uint32_t* ldsl = lds + G::PTS;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-#pragma unroll
-  for (int qq = 0; qq < G::QPW; ++qq) {
-    const int Q = wave * G::QPW + qq;
-    const int col0 = 4 * c16 + 64 * Q;
-    const int c = col0 % C;
-    const int rest = col0 / C;
-    // idle lanes of tiny tiles (fewer than 64 columns) read column block 0
+// Where quad qq of the calling lane sits in a radix-16 column stage of digit
+// stride P: its 4 adjacent columns c..c+3, its column block `rest` (restl: the
+// block it reads, 0 for the idle lanes of tiles with fewer than 64 columns),
+// the low index lo and the first row jb (row r of the digit is jb + r P).
+template <class G, int P>
+struct ColQuad {
+  int c, rest, restl, lo, jb;
+  bool active;
+  __device__ __forceinline__ explicit ColQuad(int qq) {
+    constexpr int L = G::L, R0 = G::R0, S = G::S, C = G::C;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c16 = lane & 15;
+    const int col0 = 4 * c16 + 64 * (wave * G::QPW + qq);
+    c = col0 % C;
+    rest = col0 / C;
     constexpr bool kFull = G::NCOL >= 64 * G::NQ;
-    const bool active = kFull || rest < L / 16;
-    const int restl = active ? rest : 0;
-    int lo = 0, jb = 0;
+    active = kFull || rest < L / 16;
+    restl = active ? rest : 0;
+    lo = 0;
     if constexpr (P > 1) {
       lo = restl % P;
-      jb = (restl / P) * 16 * P + lo;  // j = jb + row * P
+      jb = (restl / P) * 16 * P + lo;
     } else {
-      jb = posrev_hi<R0, S>(restl) * 16;  // j = jb + row
+      jb = posrev_hi<R0, S>(restl) * 16;
     }
+  }
+};
+
+// HBM loads of a first radix-16 column stage with P > 1 (rows 4g..4g+3 of each
+// quad at its 4 adjacent columns), issued ahead of its compute by the pipelined
+// column kernel.
+template <class G>
+struct Col16Regs {
+  u4 h[G::QPW][4], l[G::QPW][4];
+};
+template <class G, int P, bool SPLIT>
+__device__ __forceinline__ void col_stage16_load(const KParams& kp, const ColCtx& cx,
+                                                 Col16Regs<G>& r) {
+  const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int qq = 0; qq < G::QPW; ++qq) {
+    const ColQuad<G, P> q(qq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = q.jb + (4 * g + i) * P;
+      const int64_t a = cx.in_base + (int64_t)j * kp.s_in + q.c;
+      r.h[qq][i] = gld4(kp.in + a);
+      if constexpr (SPLIT) r.l[qq][i] = gld4(kp.in + kp.in_plane + a);
+      else r.l[qq][i] = u4{0, 0, 0, 0};
+    }
+  }
+}
+
+// PRE (first stage only): the stage's HBM inputs are already in `pre`.
+template <class G, int P, bool SRCG, bool SPLIT, bool XTW, bool TSTORE, bool PRE = false>
+__device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, const ColCtx& cx,
+                                            const FOps& f, const Col16Regs<G>* pre = nullptr) {
+  constexpr int L = G::L, R0 = G::R0, S = G::S, C = G::C;
+  static_assert(!PRE || (SRCG && P > 1), "prefetched inputs feed a first stage");
+  uint32_t* ldsl = lds + G::PTS;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int qq = 0; qq < G::QPW; ++qq) {
+    const ColQuad<G, P> q(qq);
+    const int c = q.c, rest = q.rest, restl = q.restl, lo = q.lo, jb = q.jb;
+    const bool active = q.active;
     u4 rh[4], rl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = jb + (4 * g + i) * P;
-      if constexpr (SRCG) {
+      if constexpr (PRE) {
+        rh[i] = pre->h[qq][i];
+        rl[i] = pre->l[qq][i];
+      } else if constexpr (SRCG) {
         const int64_t a = cx.in_base + (int64_t)j * kp.s_in + c;
         rh[i] = gld4(kp.in + a);
         if constexpr (SPLIT) rl[i] = gld4(kp.in + kp.in_plane + a);
@@ -1474,9 +1520,9 @@ __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds
 }
 
 // One workgroup's share of a column pass: workgroup index wg of the pass.
-template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
-__device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t* lds) {
-  using G = ColGeom<L, R0, C, NT>;
+// Tile `wg` of a column pass: C adjacent columns of outer block wg / blocks.
+template <bool TSTORE>
+__device__ __forceinline__ ColCtx col_ctx(const KParams& kp, int64_t wg, int C) {
   ColCtx cx;
   cx.outer = wg >> kp.blocks_log2;
   cx.i0 = (wg & (kp.blocks - 1)) * C;
@@ -1485,6 +1531,13 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
     cx.out_base = cx.outer * kp.out_outer + (cx.i0 << kp.tblk_log2);
   else
     cx.out_base = cx.outer * kp.out_outer + (cx.i0 >> kp.q_log2) * kp.qstride + (cx.i0 & (kp.q - 1));
+  return cx;
+}
+
+template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
+__device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t* lds) {
+  using G = ColGeom<L, R0, C, NT>;
+  const ColCtx cx = col_ctx<TSTORE>(kp, wg, C);
   const FOps f = load_fops<SPLIT>(kp.fimg);
   if constexpr (!SPLIT && ColFusedMx<G>::value) {
     col_stage_fused_mx<G>(kp, lds, cx);
@@ -1507,10 +1560,53 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
   }
 }
 
+// Whether a column pass runs as a pipelined persistent kernel: FP16 passes
+// whose first stage is radix-16 from HBM with P > 1, at 256 threads (the
+// 256-point columns).  Like the row pipeline, workgroup b runs tiles b, b +
+// grid, ... and issues the next tile's HBM loads while the current one runs
+// its LDS stages and stores; the register budget is capped at two waves per
+// SIMD (two 64 KB workgroups per CU).  Split passes and transposed stores keep
+// one tile per workgroup: with the held-over tile they do not fit that budget
+// (split: hi and lo planes; the transposed store spills 240 bytes per lane).
+template <class G, bool SPLIT, bool TSTORE>
+struct ColPipe {
+  static constexpr bool value = !SPLIT && !TSTORE && G::NT == 256 && G::R0 == 1 && G::S >= 2;
+};
+
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
-__global__ __launch_bounds__(NT) void col_kernel(KParams kp) {
+__device__ __forceinline__ void col_pipe(const KParams& kp, uint32_t* lds) {
+  using G = ColGeom<L, R0, C, NT>;
+  constexpr int P1 = pow16(G::S - 1);
+  const int64_t ntiles = kp.ntrans;  // column passes: the number of tiles
+  const FOps f = load_fops<SPLIT>(kp.fimg);
+  int64_t w = blockIdx.x;
+  if (w >= ntiles) return;
+  ColCtx cx = col_ctx<TSTORE>(kp, w, C);
+  Col16Regs<G> r;
+  col_stage16_load<G, P1, SPLIT>(kp, cx, r);
+  for (; w < ntiles; w += gridDim.x) {
+    col_stage16<G, P1, true, SPLIT, XTW, TSTORE, true>(kp, lds, cx, f, &r);
+    const int64_t wn = w + gridDim.x;
+    ColCtx cn = cx;
+    if (wn < ntiles) {
+      cn = col_ctx<TSTORE>(kp, wn, C);
+      col_stage16_load<G, P1, SPLIT>(kp, cn, r);
+    }
+    __syncthreads();
+    col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+    __syncthreads();  // the next tile's first stage rewrites LDS
+    cx = cn;
+  }
+}
+
+template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
+__global__ __launch_bounds__(NT, (ColPipe<ColGeom<L, R0, C, NT>, SPLIT, TSTORE>::value ? 2 : 1)) void col_kernel(
+    KParams kp) {
   extern __shared__ uint32_t lds[];
-  col_body<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, blockIdx.x, lds);
+  if constexpr (ColPipe<ColGeom<L, R0, C, NT>, SPLIT, TSTORE>::value)
+    col_pipe<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, lds);
+  else
+    col_body<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, blockIdx.x, lds);
 }
 
 // ===========================================================================

@@ -813,9 +813,9 @@ KParams make_kparams(const tcfft_plan_s* p, const DevPass& dpp, const void* in, 
   if (sp.key.kind != K_COL) {
     kp.ntrans = sp.lines_per_batch * batch;
     *grid = (kp.ntrans + sp.tpb - 1) / sp.tpb;
-  } else {
-    kp.ntrans = 0;
+  } else {  // column passes: ntrans is the number of tiles (read by the pipelined kernels)
     *grid = sp.blocks * batch * sp.outer_per_batch;
+    kp.ntrans = *grid;
   }
   kp.tw = dpp.tw;
   kp.fimg = p->fimg;
