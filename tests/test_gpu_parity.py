@@ -86,6 +86,19 @@ def test_inverse_and_roundtrip(tc, n):
     assert e.max() < 2 * FP16_TOL
 
 
+@pytest.mark.parametrize("dims,batch,sign", [((1 << 15,), 3, -1), ((1 << 15,), 3, 1),
+                                             ((128, 256), 4, -1), ((128, 512), 3, 1),
+                                             ((1 << 23,), 1, 1)])
+def test_matrix_core_radix8_stage(tc, dims, batch, sign):
+    """Plans with a 128-point FP16 column pass of 64 columns, whose radix-8
+    first stage runs on the matrix core (block-diagonal pair of radix-8 DFTs
+    with the stage twiddle folded into the operand): both directions, with
+    and without the inter-pass twiddle and transposed store."""
+    passes = tc.dry_run(dims, batch, direction=sign)["passes"]
+    assert any(p["kernel"] == "col" and p["L"] == 128 and p["C"] == 64 for p in passes), passes
+    _check(tc, dims, batch, sign=sign, seed=11)
+
+
 @pytest.mark.parametrize("dims", [(16, 16), (64, 512), (256, 256), (512, 128), (1024, 1024),
                                   (2048, 16), (128, 128), (256, 64), (32, 512), (16, 1024),
                                   (64, 64), (32, 128), (128, 64), (64, 128), (32, 256)])
