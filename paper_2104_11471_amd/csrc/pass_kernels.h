@@ -1232,9 +1232,39 @@ __device__ __forceinline__ void col_stage16_load(const KParams& kp, const ColCtx
 }
 
 // PRE (first stage only): the stage's HBM inputs are already in `pre`.
-template <class G, int P, bool SRCG, bool SPLIT, bool XTW, bool TSTORE, bool PRE = false>
+// Inter-pass twiddle factors of a last stage (P = 1): per quad and output row
+// j, a = W_M^{(ci0 / xdiv) k} and the column step b = W_M^k (xdiv = 1; else
+// unused).  Passes with a single radix-16 stage load them before their HBM
+// reads, so the table lookups overlap those reads instead of waiting at the
+// end of the pass.
+template <class G>
+struct XtwRegs {
+  float2 a[G::QPW][4], b[G::QPW][4];
+};
+template <class G>
+__device__ __forceinline__ void xtw_prefetch(const KParams& kp, const ColCtx& cx, XtwRegs<G>& x) {
+  constexpr int L = G::L;
+  const int g = (threadIdx.x & 63) >> 4;
+  const uint32_t lo_mask = (1u << kp.xbits) - 1u;
+#pragma unroll
+  for (int qq = 0; qq < G::QPW; ++qq) {
+    const ColQuad<G, 1> q(qq);
+    const uint32_t ci = (uint32_t)(kp.xoff + cx.i0 + q.c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k = (uint32_t)(q.restl + (L / 16) * (4 * g + j));
+      x.a[qq][j] = xtwiddle(kp, ci >> kp.xdiv_log2, k);
+      x.b[qq][j] = tld(kp.xtw_lo, k & lo_mask);  // k < L <= 2^xbits where xdiv = 1
+    }
+  }
+}
+
+// XPRE (last stage with XTW): the inter-pass twiddle factors are in `xp`.
+template <class G, int P, bool SRCG, bool SPLIT, bool XTW, bool TSTORE, bool PRE = false,
+          bool XPRE = false>
 __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, const ColCtx& cx,
-                                            const FOps& f, const Col16Regs<G>* pre = nullptr) {
+                                            const FOps& f, const Col16Regs<G>* pre = nullptr,
+                                            const XtwRegs<G>* xp = nullptr) {
   constexpr int L = G::L, R0 = G::R0, S = G::S, C = G::C;
   static_assert(!PRE || (SRCG && P > 1), "prefetched inputs feed a first stage");
   uint32_t* ldsl = lds + G::PTS;
@@ -1283,6 +1313,16 @@ __device__ __forceinline__ void col_stage16(const KParams& kp, uint32_t* lds, co
         const float2 v = tld(kp.tw, (4 * g + j) * lo * (L / (16 * P)));  // W_{16P}^{row lo}
 #pragma unroll
         for (int t = 0; t < 4; ++t) w[t][j] = v;
+      } else if constexpr (XTW && XPRE) {
+        const float2 a = xp->a[qq][j];
+        w[0][j] = a;
+        if (kp.xdiv == 1) {
+#pragma unroll
+          for (int t = 1; t < 4; ++t) w[t][j] = cmul(w[t - 1][j], xp->b[qq][j]);
+        } else {
+#pragma unroll
+          for (int t = 1; t < 4; ++t) w[t][j] = a;
+        }
       } else if constexpr (XTW) {
         const uint32_t k = (uint32_t)(restl + (L / 16) * (4 * g + j));  // natural output index
         const uint32_t ci = (uint32_t)(kp.xoff + cx.i0 + c);
@@ -1560,13 +1600,14 @@ __device__ __forceinline__ void col_stage_fused_mx(const KParams& kp, uint32_t* 
   }
 }
 
-template <class G, int E, bool SPLIT, bool XTW, bool TSTORE>
+template <class G, int E, bool SPLIT, bool XTW, bool TSTORE, bool XPRE = false>
 __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds, const ColCtx& cx,
-                                                const FOps& f) {
-  col_stage16<G, pow16(E), false, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+                                                const FOps& f, const XtwRegs<G>* xp = nullptr) {
+  col_stage16<G, pow16(E), false, SPLIT, XTW, TSTORE, false, XPRE && E == 0>(kp, lds, cx, f,
+                                                                            nullptr, xp);
   if constexpr (E > 0) {
     __syncthreads();
-    col_stages_from<G, E - 1, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+    col_stages_from<G, E - 1, SPLIT, XTW, TSTORE, XPRE>(kp, lds, cx, f, xp);
   }
 }
 
@@ -1598,14 +1639,21 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
     col_stage_fused<G, SPLIT>(kp, lds, cx, f);
     __syncthreads();
     col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
-  } else if constexpr (!SPLIT && ColR8Mx<G, XTW, TSTORE>::value) {
-    col_stage_r8mx<G>(kp, lds, cx);
-    __syncthreads();
-    col_stages_from<G, G::S - 1, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
   } else if constexpr (R0 > 1) {
-    col_stage_r0<G, SPLIT>(kp, lds, cx);
+    // one radix-16 stage after the radix-R0 stage: its inter-pass twiddle
+    // lookups go out before the pass's HBM reads (split: 1D 2^22 x 4 179 ->
+    // 172 us, 65536 x 2048 999 -> 983 us; FP16 with the transposed store 73.9
+    // -> 73.0 us; the FP16 first pass of the 65536-point plan measured slower,
+    // 220 -> 225 us, and keeps its lookups in the last stage)
+    constexpr bool XPRE = XTW && G::S == 1 && (SPLIT || TSTORE);
+    XtwRegs<G> xr;
+    if constexpr (XPRE) xtw_prefetch<G>(kp, cx, xr);
+    if constexpr (!SPLIT && ColR8Mx<G, XTW, TSTORE>::value)
+      col_stage_r8mx<G>(kp, lds, cx);
+    else
+      col_stage_r0<G, SPLIT>(kp, lds, cx);
     __syncthreads();
-    col_stages_from<G, G::S - 1, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
+    col_stages_from<G, G::S - 1, SPLIT, XTW, TSTORE, XPRE>(kp, lds, cx, f, &xr);
   } else {
     col_stage16<G, pow16(G::S - 1), true, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
     if constexpr (G::S > 1) {
