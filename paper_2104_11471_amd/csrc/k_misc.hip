@@ -107,41 +107,6 @@ void launch_gen_fimg_tw(void* img, int P, double sgn, double scale, hipStream_t 
                        reinterpret_cast<h8*>(img) + 256 * lo, sgn, scale, 1, 0, P, lo);
 }
 
-// Block-diagonal radix-8 operands: lane = 16 g + m holds row m, K entries of
-// input rows r = 4g..4g+3; rows and columns 0-7 belong to low index 2q, 8-15
-// to 2q + 1 (digit d = r mod 8, output k = m mod 8), entry W_L^{k (P0 d + lo)}.
-__global__ void gen_fimg8_kernel(h8* img, int L, double sgn, double scale) {
-  const int q = blockIdx.x, lane = threadIdx.x;
-  const int g = lane >> 4, m = lane & 15;
-  const int P0 = L / 8;
-  h8 rh, ih;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 4 * g + i;
-    double fr = 0.0, fi = 0.0;
-    if ((r >> 3) == (m >> 3)) {
-      const int lo = 2 * q + (m >> 3), k = m & 7, d = r & 7;
-      const int e = (k * (P0 * d + lo)) % L;
-      double sn, cs;
-      sincospi(2.0 * (double)e / (double)L, &sn, &cs);
-      fr = cs * scale;
-      fi = sgn * sn * scale;
-    }
-    // Yr row: [Fr, -Fi]; Yi row: [Fi, Fr]
-    rh[2 * i] = (_Float16)fr;
-    rh[2 * i + 1] = (_Float16)(-fi);
-    ih[2 * i] = (_Float16)fi;
-    ih[2 * i + 1] = (_Float16)fr;
-  }
-  img[256 * q + lane] = rh;
-  img[256 * q + 64 + lane] = ih;
-}
-
-void launch_gen_fimg8(void* img, int L, double sgn, double scale, hipStream_t s) {
-  hipLaunchKernelGGL(gen_fimg8_kernel, dim3(L / 16), dim3(64), 0, s, reinterpret_cast<h8*>(img),
-                     L, sgn, scale);
-}
-
 // Autotuner scratch data: FP16 complex words with re, im in [-1, 1) from a
 // hash of the word index (timing on zeros would run at unrepresentative power).
 __global__ void fill_pattern_kernel(uint32_t* p, int64_t nwords) {

@@ -171,21 +171,6 @@ void launch_gen_fimg_r(void* img, int R, double sgn, double scale, hipStream_t s
 // A_lo = diag(W_{16 P}^{k1 lo}) . F_16 scaled by `scale`, for lo = 0..P-1, at
 // img + 256 lo (h8 units), the same four images as launch_gen_fimg.
 void launch_gen_fimg_tw(void* img, int P, double sgn, double scale, hipStream_t s);
-// Radix-8 first stage of an L-point column pass on the matrix core (L = 8 P0):
-// pair q of low indices (2q, 2q + 1) is the block-diagonal 16 x 16 operand
-// diag(B_{2q}, B_{2q+1}), B_lo[k][d] = W_L^{k (P0 d + lo)} scaled by `scale`
-// (the stage's DFT, twiddle and scale), at img + 256 q (h8 units), Yr-hi and
-// Yi-hi images; q = 0 .. P0/2 - 1.
-void launch_gen_fimg8(void* img, int L, double sgn, double scale, hipStream_t s);
-// Whether a column pass takes that matrix-core radix-8 stage: FP16 128-point
-// columns, 64 per workgroup (one pair of low indices per 64-column quad).
-// Passes with the inter-pass twiddle and a natural-order store (the first
-// pass of a two-pass 65536-point plan) keep the vector-ALU stage, measured
-// faster there (221 against 225 us for 2^27 points); the others gain (1D
-// 2^22 x 4: 76.5 -> 73.9 us, 2^20 x 16: 72.6 -> 70.4 us).
-constexpr bool col_r8mx_form(int L, int R0, int C, int NT, int split, int xtw, int tstore) {
-  return !split && L == 128 && R0 == 8 && C == 64 && NT == 256 && (!xtw || tstore);
-}
 void launch_fill_pattern(void* p, int64_t nwords, hipStream_t s);
 
 // Real-input transforms around an M-point complex transform (N = 2M reals).

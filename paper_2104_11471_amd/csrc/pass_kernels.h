@@ -1118,57 +1118,6 @@ __device__ __forceinline__ void col_stage_r0(const KParams& kp, uint32_t* lds, c
   }
 }
 
-// Matrix-core form of the radix-8 first stage of a 128-point FP16 column pass:
-// the radix-8 DFTs of two low indices (2q, 2q + 1) form one block-diagonal
-// 16 x 16 product, with the stage's twiddle W_L^{k lo} and scale folded into
-// the A operand (plan table kp.fimg2, pair q at 256 q).  Each quad of the
-// workgroup covers 64 columns at one pair; lane (g, c16) holds digits
-// d = 4 (g mod 2) .. + 3 of low index 2q + g / 2 for 4 adjacent columns, and
-// its accumulators are outputs k = 4 (g mod 2) + r of the same low index.
-template <class G, bool XTW, bool TSTORE>
-struct ColR8Mx {
-  static constexpr bool value = col_r8mx_form(G::L, G::R0, G::C, G::NT, false, XTW, TSTORE) &&
-                                G::NQ == (G::L / 16) * (G::C / 64);
-};
-
-template <class G>
-__device__ __forceinline__ void col_stage_r8mx(const KParams& kp, uint32_t* lds, const ColCtx& cx) {
-  constexpr int C = G::C, P0 = G::P0, QC = C / 64;  // quads per pair
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-  const int d0 = 4 * (g & 1);
-  const TCFFT_GLOBAL h8* img = (const TCFFT_GLOBAL h8*)(kp.fimg2);
-#pragma unroll
-  for (int qq = 0; qq < G::QPW; ++qq) {
-    const int Q = wave * G::QPW + qq;
-    const int q = Q / QC, c = 64 * (Q % QC) + 4 * c16;
-    const int lo = 2 * q + (g >> 1);
-    u4 rh[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t a = cx.in_base + (int64_t)((d0 + i) * P0 + lo) * kp.s_in + c;
-      rh[i] = gld4(kp.in + a);
-    }
-    const h8 far = img[256 * q + lane];
-    const h8 fai = img[256 * q + 64 + lane];
-    uint32_t oh[4][4];  // [t][r]
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const h8 bh = __builtin_bit_cast(h8, u4{rh[0][t], rh[1][t], rh[2][t], rh[3][t]});
-      const f4 z0 = {0.f, 0.f, 0.f, 0.f};
-      const f4 yr = __builtin_amdgcn_mfma_f32_16x16x32_f16(far, bh, z0, 0, 0, 0);
-      const f4 yi = __builtin_amdgcn_mfma_f32_16x16x32_f16(fai, bh, z0, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) oh[t][r] = pack(yr[r], yi[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = cx.lds_off + ((d0 + r) * P0 + lo) * C + c;
-      lds_st4(lds, p, u4{oh[0][r], oh[1][r], oh[2][r], oh[3][r]});
-    }
-  }
-}
-
 // Extra inter-pass twiddle W_M^{ci * k} (two-level table, FP32).  M is a power
 // of two below 2^32, so the exponent needs only the low 32 bits of ci * k.
 __device__ __forceinline__ float2 xtwiddle(const KParams& kp, uint32_t ci, uint32_t k) {
@@ -1648,10 +1597,7 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
     constexpr bool XPRE = XTW && G::S == 1 && (SPLIT || TSTORE);
     XtwRegs<G> xr;
     if constexpr (XPRE) xtw_prefetch<G>(kp, cx, xr);
-    if constexpr (!SPLIT && ColR8Mx<G, XTW, TSTORE>::value)
-      col_stage_r8mx<G>(kp, lds, cx);
-    else
-      col_stage_r0<G, SPLIT>(kp, lds, cx);
+    col_stage_r0<G, SPLIT>(kp, lds, cx);
     __syncthreads();
     col_stages_from<G, G::S - 1, SPLIT, XTW, TSTORE, XPRE>(kp, lds, cx, f, &xr);
   } else {

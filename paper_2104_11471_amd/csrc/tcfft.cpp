@@ -740,12 +740,6 @@ tcfft_status create_device_plan(const PlanSpec& ps, tcfft_plan_s** out) {
         if ((st = dev_alloc(p, (size_t)r0 * 256 * 16, &dpp.fimg2))) break;
         // both stages' scales: 2^-1 (radix 2 or 4) and 2^-2 (radix 16)
         launch_gen_fimg_r(dpp.fimg2, r0, sgn, noscale ? 1.0 : 0.125, s);
-      } else if (sp.key.kind == K_COL && col_r8mx_form(sp.key.L, sp.key.R0, sp.key.C, sp.key.NT,
-                                                       sp.key.split, sp.key.xtw, sp.key.tstore)) {
-        // the matrix-core radix-8 stage: its scale is the pass's radix-R0 scale
-        if ((st = dev_alloc(p, (size_t)(sp.key.L / 16) * 256 * 16, &dpp.fimg2))) break;
-        launch_gen_fimg8(dpp.fimg2, sp.key.L, sgn,
-                         noscale ? 1.0 : std::ldexp(1.0, -(sp.scale - 2 * s16_of(sp.key.L))), s);
       }
       if (sp.key.kind != K_BIG) {  // read by FP16 stride-16 stages that fold their twiddle
         if ((st = dev_alloc(p, (size_t)16 * 256 * 16, &dpp.fimg3))) break;

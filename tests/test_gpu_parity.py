@@ -89,14 +89,24 @@ def test_inverse_and_roundtrip(tc, n):
 @pytest.mark.parametrize("dims,batch,sign", [((1 << 15,), 3, -1), ((1 << 15,), 3, 1),
                                              ((128, 256), 4, -1), ((128, 512), 3, 1),
                                              ((1 << 23,), 1, 1)])
-def test_matrix_core_radix8_stage(tc, dims, batch, sign):
-    """Plans with a 128-point FP16 column pass of 64 columns, whose radix-8
-    first stage runs on the matrix core (block-diagonal pair of radix-8 DFTs
-    with the stage twiddle folded into the operand): both directions, with
-    and without the inter-pass twiddle and transposed store."""
+def test_128_point_column_passes(tc, dims, batch, sign):
+    """Plans with a 128-point FP16 column pass of 64 columns (radix-8 stage,
+    then one radix-16 stage): both directions, with the inter-pass twiddle
+    and transposed store (its table lookups issued before the HBM reads) and
+    without."""
     passes = tc.dry_run(dims, batch, direction=sign)["passes"]
     assert any(p["kernel"] == "col" and p["L"] == 128 and p["C"] == 64 for p in passes), passes
     _check(tc, dims, batch, sign=sign, seed=11)
+
+
+@pytest.mark.parametrize("n,sign", [(1 << 15, -1), (1 << 15, 1), (1 << 23, -1)])
+def test_split_early_twiddle_lookups(tc, n, sign):
+    """Split plans whose 128-point first pass (radix-8 stage, then one radix-16
+    stage with the inter-pass twiddle) loads that twiddle's table entries
+    before its HBM reads."""
+    passes = tc.dry_run((n,), 1, direction=sign, precision="split")["passes"]
+    assert passes[0]["kernel"] == "col" and passes[0]["L"] == 128 and passes[0]["xtw"] == 1, passes
+    _check(tc, (n,), 3 if n <= (1 << 15) else 1, prec="split", sign=sign, seed=12)
 
 
 @pytest.mark.parametrize("dims", [(16, 16), (64, 512), (256, 256), (512, 128), (1024, 1024),
