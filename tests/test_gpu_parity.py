@@ -99,6 +99,19 @@ def test_128_point_column_passes(tc, dims, batch, sign):
     _check(tc, dims, batch, sign=sign, seed=11)
 
 
+@pytest.mark.parametrize("dims,batch,sign", [((256, 256), 1, -1), ((256, 256), 129, -1),
+                                             ((256, 256), 300, 1), ((1 << 16,), 257, -1),
+                                             ((256, 1024), 33, 1)])
+def test_pipelined_256_point_column_passes(tc, dims, batch, sign):
+    """FP16 256-point column passes run as persistent kernels that prefetch the
+    next tile: tile counts below, just above and well above the resident
+    grid (ragged last round), both directions, 2D and the second pass of a
+    65536-point plan."""
+    passes = tc.dry_run(dims, batch, direction=sign)["passes"]
+    assert any(p["kernel"] == "col" and p["L"] == 256 and not p["tstore"] for p in passes), passes
+    _check(tc, dims, batch, sign=sign, seed=13)
+
+
 @pytest.mark.parametrize("n,sign", [(1 << 15, -1), (1 << 15, 1), (1 << 23, -1)])
 def test_split_early_twiddle_lookups(tc, n, sign):
     """Split plans whose 128-point first pass (radix-8 stage, then one radix-16
