@@ -192,7 +192,7 @@ int fused_variant(const KernelKey& k) {
   for (int i = 0; i < kNumFused; ++i) {
     const FusedVariant& v = kFused[i];
     if (v.kind == k.kind && v.L == k.L && v.R0 == k.R0 && v.C == k.C && v.split == k.split &&
-        (k.kind != K_COL || v.xtw == k.xtw) && v.tstore == k.tstore)
+        v.xtw == k.xtw && v.tstore == k.tstore)
       return i;
   }
   return -1;
