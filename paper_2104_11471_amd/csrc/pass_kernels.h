@@ -1180,7 +1180,6 @@ __device__ __forceinline__ void col_stage16_load(const KParams& kp, const ColCtx
   }
 }
 
-// PRE (first stage only): the stage's HBM inputs are already in `pre`.
 // Inter-pass twiddle factors of a last stage (P = 1): per quad and output row
 // j, a = W_M^{(ci0 / xdiv) k} and the column step b = W_M^k (xdiv = 1; else
 // unused).  Passes with a single radix-16 stage load them before their HBM
@@ -1208,6 +1207,7 @@ __device__ __forceinline__ void xtw_prefetch(const KParams& kp, const ColCtx& cx
   }
 }
 
+// PRE (first stage only): the stage's HBM inputs are already in `pre`.
 // XPRE (last stage with XTW): the inter-pass twiddle factors are in `xp`.
 template <class G, int P, bool SRCG, bool SPLIT, bool XTW, bool TSTORE, bool PRE = false,
           bool XPRE = false>
@@ -1560,7 +1560,6 @@ __device__ __forceinline__ void col_stages_from(const KParams& kp, uint32_t* lds
   }
 }
 
-// One workgroup's share of a column pass: workgroup index wg of the pass.
 // Tile `wg` of a column pass: C adjacent columns of outer block wg / blocks.
 template <bool TSTORE>
 __device__ __forceinline__ ColCtx col_ctx(const KParams& kp, int64_t wg, int C) {
@@ -1575,6 +1574,7 @@ __device__ __forceinline__ ColCtx col_ctx(const KParams& kp, int64_t wg, int C) 
   return cx;
 }
 
+// One workgroup's share of a column pass: workgroup index wg of the pass.
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
 __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t* lds) {
   using G = ColGeom<L, R0, C, NT>;
@@ -1590,10 +1590,11 @@ __device__ __forceinline__ void col_body(const KParams& kp, int64_t wg, uint32_t
     col_stages_from<G, G::S - 2, SPLIT, XTW, TSTORE>(kp, lds, cx, f);
   } else if constexpr (R0 > 1) {
     // one radix-16 stage after the radix-R0 stage: its inter-pass twiddle
-    // lookups go out before the pass's HBM reads (split: 1D 2^22 x 4 179 ->
-    // 172 us, 65536 x 2048 999 -> 983 us; FP16 with the transposed store 73.9
-    // -> 73.0 us; the FP16 first pass of the 65536-point plan measured slower,
-    // 220 -> 225 us, and keeps its lookups in the last stage)
+    // lookups go out before the pass's HBM reads (split: 1D 2^22 x 4 177 ->
+    // 171 us, 65536 x 2048 998 -> 983 us; FP16 with the transposed store:
+    // 2^15 x 4096 413 -> 397 us, 2^20 x 16 72.7 -> 70.4 us; the FP16 first
+    // pass of the 65536-point plan measured slower, 220 -> 225 us, and keeps
+    // its lookups in the last stage)
     constexpr bool XPRE = XTW && G::S == 1 && (SPLIT || TSTORE);
     XtwRegs<G> xr;
     if constexpr (XPRE) xtw_prefetch<G>(kp, cx, xr);
@@ -1649,8 +1650,8 @@ __device__ __forceinline__ void col_pipe(const KParams& kp, uint32_t* lds) {
 }
 
 template <int L, int R0, int C, int NT, bool SPLIT, bool XTW, bool TSTORE>
-__global__ __launch_bounds__(NT, (ColPipe<ColGeom<L, R0, C, NT>, SPLIT, TSTORE>::value ? 2 : 1)) void col_kernel(
-    KParams kp) {
+__global__ __launch_bounds__(NT, (ColPipe<ColGeom<L, R0, C, NT>, SPLIT, TSTORE>::value ? 2 : 1))
+void col_kernel(KParams kp) {
   extern __shared__ uint32_t lds[];
   if constexpr (ColPipe<ColGeom<L, R0, C, NT>, SPLIT, TSTORE>::value)
     col_pipe<L, R0, C, NT, SPLIT, XTW, TSTORE>(kp, lds);
